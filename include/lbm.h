@@ -1,0 +1,180 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) thermal pseudopotential D3Q19 lattice
+ * Boltzmann step.
+ *
+ * The method is the two-population scheme of Biferale, Perlekar, Sbragaglia &
+ * Toschi, "Convection in multiphase flows using Lattice Boltzmann methods"
+ * (arXiv:1111.0905), section "Algorithm": eqs. (LBEQ)/(LBEQ2) for the mass
+ * populations f and the rho*T populations g, eq. (HYDRO) for the moments,
+ * eq. (FORCE) for the pseudopotential force with psi = exp(-1/rho), the
+ * velocity shift u' = u + tau_nu F / rho, the f/g coupling giving the ideal
+ * pressure rho T, and a counter-term in the g dynamics giving the
+ * compressive work P0 div u of eq. (eq).  Walls at the bottom and top are
+ * no-slip with imposed temperatures T_d / T_u (Fig. 1 caption, text before
+ * eq. (heat2)); x and y are periodic.
+ *
+ * Lattice and layout
+ * ------------------
+ * Nodes (i, j, k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz; the walls sit
+ * half a spacing below k = 0 and above k = nz-1 (cell height H = nz).
+ * D3Q19 velocities, in this order (an interface: state buffers use it):
+ *    0:( 0, 0, 0)
+ *    1:(+1, 0, 0)  2:(-1, 0, 0)  3:( 0,+1, 0)  4:( 0,-1, 0)  5:( 0, 0,+1)  6:( 0, 0,-1)
+ *    7:(+1,+1, 0)  8:(-1,-1, 0)  9:(+1,-1, 0) 10:(-1,+1, 0)
+ *   11:(+1, 0,+1) 12:(-1, 0,-1) 13:(+1, 0,-1) 14:(-1, 0,+1)
+ *   15:( 0,+1,+1) 16:( 0,-1,-1) 17:( 0,+1,-1) 18:( 0,-1,+1)
+ * A canonical state is 38 * N doubles, N = nx*ny*nz: population q
+ * (q < 19: f_q, q >= 19: g_{q-19}) of node (i,j,k) at
+ *   state[((q * nz + k) * ny + j) * nx + i],
+ * holding the post-streaming populations at the current time level.
+ * Fields are (nz, ny, nx) row-major, i fastest.
+ *
+ * Memory ownership
+ * ----------------
+ * The caller owns every buffer.  The library never allocates device memory:
+ * lbm_init carves its two population buffers and its scratch out of one
+ * caller-provided device workspace of lbm_workspace_bytes() bytes, which must
+ * stay alive (and untouched) until lbm_destroy.  Pointers documented "device"
+ * must be device memory of the current HIP device; "host" pointers are host
+ * memory.  All work is enqueued on the HIP stream given to lbm_init (NULL =
+ * the default stream).
+ *
+ * Errors
+ * ------
+ * Functions return 0 on success or a negative LBM_E* code; lbm_last_error()
+ * returns a thread-local message describing the last failure.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage of the populations; arithmetic is FP64 for LBM_FP64, FP32 else */
+enum {
+  LBM_FP64 = 0,      /* double storage, double arithmetic */
+  LBM_FP32 = 1,      /* float storage, float arithmetic */
+  LBM_FP16DEV = 2,   /* IEEE half of (pop - reference pop), float arithmetic */
+  LBM_BF16DEV = 3    /* bfloat16 of (pop - reference pop), float arithmetic */
+};
+
+/* which implementation of the step */
+enum {
+  LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step, next plane kept in registers (default) */
+  LBM_KERNEL_REFERENCE = 1,    /* two plain kernels per step (moments, then collide+stream) */
+  LBM_KERNEL_FUSED_RELOAD = 2  /* one z-marching kernel per step, populations re-read from cache */
+};
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument or parameter */
+  LBM_EWORKSPACE = -2,  /* workspace too small or misaligned */
+  LBM_EHIP = -3,        /* a HIP runtime call failed */
+  LBM_ENUMERIC = -4     /* a diagnostic found a non-finite value or rho <= 0 */
+};
+
+/*
+ * Problem statement (eqs. (ns), (LBEQ)-(FORCE), Table 1).
+ *   tau_nu, tau_kappa > 1/2: relaxation times of f and g;
+ *     nu = (tau_nu - 1/2)/3, kappa = c_v (tau_kappa - 1/2) rho_kappa / 3.
+ *   G: strength of eq. (FORCE), G < 0 (attraction); critical point
+ *     rho_c = 1, T_c = -G / e^2, bulk pressure rho T + (G/2) exp(-2/rho).
+ *   T_d, T_u > 0: bottom and top wall temperatures.
+ *   gravity >= 0: body force rho * (0, 0, -gravity).
+ *   c_v > 0: specific heat at constant volume.
+ *   rho_kappa > 0: density that sets the conductivity of g^eq.
+ *   rho_ref, T_ref: reference state of the FP16/BF16 deviation storage
+ *     (pop_ref = equilibrium at rest of (rho_ref, T_ref)); ignored otherwise.
+ *   periodic_z: 0 = walls (nz >= 2), 1 = periodic in z as well.
+ *   kernel: LBM_KERNEL_*; tile_y: rows per fused-kernel tile (0 = default).
+ */
+typedef struct lbm_params {
+  int32_t nx, ny, nz;
+  int32_t storage;
+  int32_t periodic_z;
+  int32_t kernel;
+  int32_t tile_y;
+  int32_t z_chunk;     /* planes per fused-kernel work-group column (0 = default) */
+  double tau_nu, tau_kappa;
+  double G;
+  double T_d, T_u;
+  double gravity;
+  double c_v;
+  double rho_kappa;
+  double rho_ref, T_ref;
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Library version string (static storage). */
+const char* lbm_version(void);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* lbm_last_error(void);
+
+/* Bytes of device workspace lbm_init needs for these parameters, or 0 if the
+ * parameters are invalid (then lbm_last_error says why). */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/*
+ * Set up a lattice at rest in local equilibrium (Algorithm section):
+ *   f = f^eq(rho0, u = 0),  g = g^eq(rho0 T0, v = 0).
+ * rho0: device, N doubles (> 0), the initial density field.
+ * T0:   device, N doubles, or NULL for the conduction profile
+ *       T0(k) = T_d + (T_u - T_d)(k + 1/2)/nz.
+ * workspace: device, >= lbm_workspace_bytes(p) bytes, 256-byte aligned;
+ *   owned by the caller, used by the handle until lbm_destroy.
+ * stream: hipStream_t (as void*) on which all work of this handle runs.
+ * On success *out is a new handle (host memory owned by the library).
+ * Synchronous with respect to the stream on return.
+ */
+int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes,
+             const double* rho0, const double* T0, void* stream, lbm_handle** out);
+
+/* Advance n >= 0 time steps (asynchronous on the handle's stream). */
+int lbm_step(lbm_handle* h, int64_t n);
+
+/* Number of steps taken since lbm_init / lbm_set_state. */
+int64_t lbm_time(const lbm_handle* h);
+
+/*
+ * Global FP64 diagnostics of the current state (eqs. (HYDRO), (internal)):
+ * totals (host, 6 doubles) = [sum rho, sum rho v_x, sum rho v_y, sum rho v_z,
+ *   sum rho T, sum rho U] with v = (j + F/2)/rho the physical velocity and
+ *   U = c_v T + (G/4) exp(-2/rho) the internal energy.
+ * fields (device, 5*N doubles, or NULL): rho, v_x, v_y, v_z, T.
+ * Synchronises the stream.  Returns LBM_ENUMERIC if a value is non-finite or
+ * rho <= 0 somewhere.
+ */
+int lbm_moments(lbm_handle* h, double* totals, double* fields);
+
+/*
+ * Nusselt numbers (eq. (flux), Fig. 2 bottom) in units of kappa (T_d-T_u)/nz:
+ *   nu_bot = 2 nz (T_d - Tbar(0)) / (T_d - T_u)  (half-cell wall flux),
+ *   nu_top = 2 nz (Tbar(nz-1) - T_u) / (T_d - T_u),
+ *   nu_z[k] = [<rho U v_z>(k) - kappa (Tbar(k+1) - Tbar(k-1))/2] nz / (kappa (T_d-T_u))
+ *     with ghost planes Tbar(-1) = 2 T_d - Tbar(0), Tbar(nz) = 2 T_u - Tbar(nz-1),
+ *   T_z[k] = Tbar(k), the horizontal mean of T.
+ * nu_bot, nu_top: host, may be NULL; nu_z, T_z: host, nz doubles, may be NULL.
+ * Synchronises the stream.  Needs walls and T_d != T_u (else LBM_EINVAL).
+ */
+int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, double* T_z);
+
+/* Copy the current state to / from a canonical FP64 state (device, 38*N
+ * doubles, layout above).  set_state encodes to the handle's storage and
+ * resets lbm_time to 0.  Both are asynchronous on the stream. */
+int lbm_get_state(lbm_handle* h, double* state);
+int lbm_set_state(lbm_handle* h, const double* state);
+
+/* Release the handle (the workspace stays the caller's). */
+void lbm_destroy(lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

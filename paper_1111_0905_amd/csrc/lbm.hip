@@ -1,0 +1,874 @@
+// lbm.hip - HIP kernels (gfx950) and the C ABI of the thermal pseudopotential
+// D3Q19 lattice Boltzmann step (arXiv:1111.0905, section "Algorithm").
+// The ABI is declared and documented in include/lbm.h.
+//
+// Data layout in HBM: structure of arrays, population q of node (i, j, k) at
+// q * N + (k * ny + j) * nx + i (i fastest), two ping-pong buffers holding
+// the post-streaming populations.  Streaming is a push: the collided value of
+// node x in direction l is written to x + c_l of the other buffer; at the
+// walls it is written back to x in direction opp(l) (half-way bounce-back for
+// f, anti-bounce-back about w_l rho_kappa T_wall for g).
+//
+// Kernels
+//   k_fused      one launch per step: a work-group owns a 64 x TY column of
+//                the x-y plane and marches up a chunk of z planes; rho, E and
+//                psi of the current plane and its two neighbours (tile plus a
+//                one-node ring) sit in an LDS ring buffer, so every population
+//                is read from HBM once and written once per step.
+//   k_rhoE +     reference two-pass step (and the diagnostics): rho and E of
+//   k_collide    every node to scratch, then collide+stream per node.
+//   k_diag, k_plane, k_finish_*   FP64 reductions for the diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "physics.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(LBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+// 32-bit node offset (the library limits N to < 2^31 nodes).
+__device__ __forceinline__ uint32_t node_off(int i, int j, int k, int nx, int ny) {
+  return ((uint32_t)k * (uint32_t)ny + (uint32_t)j) * (uint32_t)nx + (uint32_t)i;
+}
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Push-stream the collided values of node (i, j, k) into `out`.
+template <typename C, typename R = typename C::R>
+struct Streamer {
+  typename C::S* out;
+  const DevParams<R>& P;
+  size_t N;
+  int i, j, k, im, ip, jm, jp;
+  __device__ __forceinline__ void operator()(int l, R fs, R gs) const {
+    const int nz = P.nz;
+    int kk = k + CZ[l];
+    int ii = CX[l] > 0 ? ip : (CX[l] < 0 ? im : i);
+    int jj = CY[l] > 0 ? jp : (CY[l] < 0 ? jm : j);
+    int q = l;
+    if (kk < 0 || kk >= nz) {
+      if (P.periodic_z) {
+        kk = kk < 0 ? kk + nz : kk - nz;
+      } else {  // the wall sends it back into this node in the opposite direction
+        const R Tw = kk < 0 ? P.T_d : P.T_u;
+        q = OPP[l];
+        ii = i;
+        jj = j;
+        kk = k;
+        gs = -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw;
+      }
+    }
+    const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
+    Codec<C>::st(out + (size_t)q * N, o, fs, P.fref[q]);
+    Codec<C>::st(out + (size_t)(q + Q) * N, o, gs, P.gref[q]);
+  }
+};
+
+template <typename C, typename R = typename C::R>
+__device__ __forceinline__ void load_node(const typename C::S* __restrict__ in, size_t N, uint32_t o,
+                                          const DevParams<R>& P, R* f, R* g) {
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    f[l] = Codec<C>::ld(in + (size_t)l * N, o, P.fref[l]);
+    g[l] = Codec<C>::ld(in + (size_t)(l + Q) * N, o, P.gref[l]);
+  }
+}
+
+// ---------------------------------------------------------------- init / state
+
+template <typename C, typename R = typename C::R>
+__global__ void k_init(typename C::S* out, const double* __restrict__ rho0,
+                       const double* __restrict__ T0, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    R T;
+    if (T0) {
+      T = (R)T0[n];
+    } else {  // conduction profile between the half-way walls
+      T = (R)((double)P.T_d + ((double)P.T_u - (double)P.T_d) * ((double)k + 0.5) / (double)P.nz);
+    }
+    R f[Q], g[Q];
+    rest_equilibrium<R>((R)rho0[n], T, P, f, g);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, f[l], P.fref[l]);
+      Codec<C>::st(out + (size_t)(l + Q) * N, (uint32_t)n, g[l], P.gref[l]);
+    }
+  }
+}
+
+template <typename C, typename R = typename C::R>
+__global__ void k_get_state(const typename C::S* __restrict__ in, double* __restrict__ st,
+                            DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t M = (size_t)2 * Q * N;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < M;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(n / N);
+    st[n] = (double)Codec<C>::ld(in + (size_t)q * N, (uint32_t)(n - (size_t)q * N),
+                                 q < Q ? P.fref[q] : P.gref[q - Q]);
+  }
+}
+
+template <typename C, typename R = typename C::R>
+__global__ void k_set_state(typename C::S* out, const double* __restrict__ st, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t M = (size_t)2 * Q * N;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < M;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(n / N);
+    Codec<C>::st(out + (size_t)q * N, (uint32_t)(n - (size_t)q * N), (R)st[n],
+                 q < Q ? P.fref[q] : P.gref[q - Q]);
+  }
+}
+
+// ---------------------------------------------------------------- reference path
+
+// rho and E of every node into scratch.
+template <typename C, typename R = typename C::R>
+__global__ void k_rhoE(const typename C::S* __restrict__ in, R* __restrict__ srho,
+                       R* __restrict__ sE, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    R rho, E;
+    moments<R>(f, g, rho, E);
+    srho[n] = rho;
+    sE[n] = E;
+  }
+}
+
+// Neighbour values from scratch with the wall ghosts: psi from the mirrored
+// density, rho and E extrapolated linearly through the wall.
+template <typename R>
+struct ScratchNb {
+  const R* srho;
+  const R* sE;
+  const DevParams<R>& P;
+  int i, j, k;
+  // which: 0 = psi, 1 = rho, 2 = E
+  __device__ __forceinline__ R get(int which, int l) const {
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int ii = wrap(i + CX[l], nx), jj = wrap(j + CY[l], ny);
+    int kk = k + CZ[l];
+    const R* a = which == 2 ? sE : srho;
+    if (kk >= 0 && kk < nz) {
+      const R v = a[node_off(ii, jj, kk, nx, ny)];
+      return which == 0 ? psi_of<R>(v) : v;
+    }
+    if (P.periodic_z) {
+      kk = kk < 0 ? kk + nz : kk - nz;
+      const R v = a[node_off(ii, jj, kk, nx, ny)];
+      return which == 0 ? psi_of<R>(v) : v;
+    }
+    const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
+    const int ki = kk < 0 ? 1 : nz - 2;     // next plane inside
+    const R v0 = a[node_off(ii, jj, kw, nx, ny)];
+    if (which == 0) return psi_of<R>(v0);
+    const R v1 = a[node_off(ii, jj, ki, nx, ny)];
+    return R(2) * v0 - v1;
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ Macro<R> macro_from_scratch(const R* f, const R* g, const ScratchNb<R>& nb,
+                                                       const DevParams<R>& P) {
+  R rho, E;
+  moments<R>(f, g, rho, E);
+  R gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz;
+  grad_w<R>([&](int l) { return nb.get(0, l); }, gpx, gpy, gpz);
+  grad_w<R>([&](int l) { return nb.get(2, l); }, gEx, gEy, gEz);
+  grad_w<R>([&](int l) { return nb.get(1, l); }, grx, gry, grz);
+  return node_macro<R>(f, g, rho, E, psi_of<R>(rho), gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
+}
+
+template <typename C, typename R = typename C::R>
+__global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* __restrict__ out,
+                          const R* __restrict__ srho, const R* __restrict__ sE, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
+    Streamer<C> em{out, P, N, i, j, k, wrap(i - 1, P.nx), wrap(i + 1, P.nx),
+                   wrap(j - 1, P.ny), wrap(j + 1, P.ny)};
+    collide<R>(f, g, m, P, em);
+  }
+}
+
+// ---------------------------------------------------------------- fused path
+
+// One work-group: tile of 64 x TY nodes in x-y, planes [k0, k1) in z.
+// LDS ring buffer of three planes of psi, rho and E over the tile plus a
+// one-node ring; the populations of the plane being collided and of the next
+// plane are held in registers, so each population is read once from HBM.
+template <typename C, int TY, bool KEEP, typename R = typename C::R>
+__global__ __launch_bounds__(64 * TY) void k_fused(const typename C::S* __restrict__ in,
+                                                  typename C::S* __restrict__ out,
+                                                  DevParams<R> P, int ntx, int nty, int kz) {
+  constexpr int TX = 64, PW = TX + 2, PN = PW * (TY + 2);
+  __shared__ R sPsi[3][PN];
+  __shared__ R sRho[3][PN];
+  __shared__ R sE[3][PN];
+
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const size_t N = (size_t)nx * ny * nz;
+
+  // XCD-aware tile order: consecutive tiles land on the same XCD (work-groups
+  // are dealt round-robin over the 8 XCDs), so neighbouring tiles share L2.
+  int bid = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int tx = bid % ntx;
+  const int rem = bid / ntx;
+  const int ty = rem % nty;
+  const int zc = rem / nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = zc * kz;
+  const int k1 = min(k0 + kz, nz);
+  const int tw = min(TX, nx - x0), th = min(TY, ny - y0);
+
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = t / TX;
+  const bool active = lx < tw && ly < th;
+  const int i = x0 + lx, j = y0 + ly;
+  const int im = wrap(i - 1, nx), ip = wrap(i + 1, nx), jm = wrap(j - 1, ny), jp = wrap(j + 1, ny);
+  const int own_s = (ly + 1) * PW + (lx + 1);
+
+  // the one-node ring around the tile: 2 (tw + 2) + 2 th nodes, dealt to the
+  // threads in turn
+  constexpr int NT = 64 * TY;
+  const int nring = 2 * (tw + 2) + 2 * th;
+  auto ring_xy = [&](int r, int& rx, int& ry) {
+    if (r < tw + 2) {
+      rx = r - 1;
+      ry = -1;
+    } else if (r < 2 * (tw + 2)) {
+      rx = r - (tw + 2) - 1;
+      ry = th;
+    } else {
+      const int q = r - 2 * (tw + 2);
+      rx = q < th ? -1 : tw;
+      ry = q < th ? q : q - th;
+    }
+  };
+
+  auto slot = [&](int kp) { return ((kp - k0) % 3 + 3) % 3; };
+
+  // rho, E, psi of plane kp (global index, already wrapped) into LDS slot s;
+  // the own populations are left in f, g when KEEP (else they are reloaded
+  // from cache when the plane is collided).
+  auto fill = [&](int kp, int s, R* f, R* g) {
+    if (active) {
+      R rho, E;
+      if (KEEP) {
+        load_node<C>(in, N, node_off(i, j, kp, nx, ny), P, f, g);
+        moments<R>(f, g, rho, E);
+      } else {
+        R ft[Q], gt[Q];
+        load_node<C>(in, N, node_off(i, j, kp, nx, ny), P, ft, gt);
+        moments<R>(ft, gt, rho, E);
+      }
+      sRho[s][own_s] = rho;
+      sE[s][own_s] = E;
+      sPsi[s][own_s] = psi_of<R>(rho);
+    }
+    for (int r = t; r < nring; r += NT) {
+      int rx, ry;
+      ring_xy(r, rx, ry);
+      const int ring_s = (ry + 1) * PW + (rx + 1);
+      R fr[Q], gr[Q];
+      load_node<C>(in, N, node_off(wrap(x0 + rx, nx), wrap(y0 + ry, ny), kp, nx, ny), P, fr, gr);
+      R rho, E;
+      moments<R>(fr, gr, rho, E);
+      sRho[s][ring_s] = rho;
+      sE[s][ring_s] = E;
+      sPsi[s][ring_s] = psi_of<R>(rho);
+    }
+  };
+  // wall ghost plane: psi mirrored, rho and E extrapolated linearly
+  auto ghost = [&](int sg, int sw, int si) {
+    for (int q = t; q < PN; q += NT) {
+      sPsi[sg][q] = sPsi[sw][q];
+      sRho[sg][q] = R(2) * sRho[sw][q] - sRho[si][q];
+      sE[sg][q] = R(2) * sE[sw][q] - sE[si][q];
+    }
+  };
+
+  R fa[Q], ga[Q], fb[Q], gb[Q];
+  const bool walls = !P.periodic_z;
+  if (k0 > 0)
+    fill(k0 - 1, slot(k0 - 1), fb, gb);
+  else if (!walls)
+    fill(nz - 1, slot(k0 - 1), fb, gb);
+  fill(k0, slot(k0), fa, ga);
+
+  for (int k = k0; k < k1; ++k) {
+    const int kn = k + 1;
+    if (kn < nz)
+      fill(kn, slot(kn), fb, gb);
+    else if (!walls)
+      fill(0, slot(kn), fb, gb);
+    __syncthreads();
+    if (walls && (k == 0 || kn == nz)) {
+      if (k == 0) ghost(slot(-1), slot(0), slot(1));
+      if (kn == nz) ghost(slot(kn), slot(k), slot(k - 1));
+      __syncthreads();
+    }
+    if (active) {
+      if (!KEEP) load_node<C>(in, N, node_off(i, j, k, nx, ny), P, fa, ga);
+      const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
+      auto at = [&](const R(*A)[PN], int l) {
+        const int s = CZ[l] < 0 ? sm : (CZ[l] > 0 ? sp : s0);
+        return A[s][own_s + CY[l] * PW + CX[l]];
+      };
+      R gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz;
+      grad_w<R>([&](int l) { return at(sPsi, l); }, gpx, gpy, gpz);
+      grad_w<R>([&](int l) { return at(sE, l); }, gEx, gEy, gEz);
+      grad_w<R>([&](int l) { return at(sRho, l); }, grx, gry, grz);
+      const Macro<R> m = node_macro<R>(fa, ga, sRho[s0][own_s], sE[s0][own_s], sPsi[s0][own_s],
+                                       gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
+      Streamer<C> em{out, P, N, i, j, k, im, ip, jm, jp};
+      collide<R>(fa, ga, m, P, em);
+    }
+    __syncthreads();
+    if (KEEP) {
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        fa[l] = fb[l];
+        ga[l] = gb[l];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x / 64); ++q) s += sh[q];
+  return s;  // valid in thread 0
+}
+
+// Per node: fields (optional) and block partial sums of
+// [rho, rho vx, rho vy, rho vz, rho T, rho U, #bad].
+template <typename C, typename R = typename C::R>
+__global__ __launch_bounds__(256) void k_diag(const typename C::S* __restrict__ in,
+                                              const R* __restrict__ srho, const R* __restrict__ sE,
+                                              DevParams<R> P, double c_v, double G,
+                                              double* __restrict__ fields,
+                                              double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
+    const double rho = m.rho, T = m.T;
+    const double U = c_v * T + 0.25 * G * exp(-2.0 / rho);
+    acc[0] += rho;
+    acc[1] += rho * (double)m.vx;
+    acc[2] += rho * (double)m.vy;
+    acc[3] += rho * (double)m.vz;
+    acc[4] += (double)m.E;
+    acc[5] += rho * U;
+    const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite((double)m.vx) ||
+                     !isfinite((double)m.vy) || !isfinite((double)m.vz);
+    acc[6] += bad ? 1.0 : 0.0;
+    if (fields) {
+      fields[n] = rho;
+      fields[N + n] = m.vx;
+      fields[2 * N + n] = m.vy;
+      fields[3 * N + n] = m.vz;
+      fields[4 * N + n] = T;
+    }
+  }
+  for (int q = 0; q < 7; ++q) {
+    const double s = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * 8 + q] = s;
+  }
+}
+
+// Fixed-order sum of the block partials (deterministic).
+__global__ __launch_bounds__(256) void k_finish_totals(const double* __restrict__ partials,
+                                                       int nblk, double* __restrict__ out) {
+  __shared__ double sh[4];
+  for (int q = 0; q < 7; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partials[(size_t)b * 8 + q];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) out[q] = s;
+  }
+}
+
+// Horizontal averages per plane: prof[2k] = mean T, prof[2k+1] = mean rho U v_z.
+template <typename C, typename R = typename C::R>
+__global__ __launch_bounds__(256) void k_plane(const typename C::S* __restrict__ in,
+                                               const R* __restrict__ srho, const R* __restrict__ sE,
+                                               DevParams<R> P, double c_v, double G,
+                                               double* __restrict__ prof) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const int plane = P.nx * P.ny;
+  double sT = 0.0, sF = 0.0;
+  for (int q = threadIdx.x; q < plane; q += blockDim.x) {
+    const int i = q % P.nx, j = q / P.nx;
+    const uint32_t n = node_off(i, j, k, P.nx, P.ny);
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
+    const double rho = m.rho, T = m.T;
+    const double U = c_v * T + 0.25 * G * exp(-2.0 / rho);
+    sT += T;
+    sF += rho * U * (double)m.vz;
+  }
+  const double a = block_sum(sT, sh);
+  const double b = block_sum(sF, sh);
+  if (threadIdx.x == 0) {
+    prof[2 * k] = a / plane;
+    prof[2 * k + 1] = b / plane;
+  }
+}
+
+// Nusselt numbers from the plane profiles; out = [nu_bot, nu_top, nu_z[nz], T_z[nz]].
+__global__ void k_finish_nusselt(const double* __restrict__ prof, int nz, double T_d, double T_u,
+                                 double kappa, double* __restrict__ out) {
+  const double dT = T_d - T_u;
+  for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+    const double Tk = prof[2 * k];
+    const double Tm = k > 0 ? prof[2 * (k - 1)] : 2.0 * T_d - prof[0];
+    const double Tp = k < nz - 1 ? prof[2 * (k + 1)] : 2.0 * T_u - prof[2 * (nz - 1)];
+    out[2 + k] = (prof[2 * k + 1] - kappa * 0.5 * (Tp - Tm)) * nz / (kappa * dT);
+    out[2 + nz + k] = Tk;
+  }
+  if (threadIdx.x == 0) {
+    out[0] = 2.0 * nz * (T_d - prof[0]) / dT;
+    out[1] = 2.0 * nz * (prof[2 * (nz - 1)] - T_u) / dT;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case LBM_FP64: return 8;
+    case LBM_FP32: return 4;
+    default: return 2;
+  }
+}
+size_t real_bytes(int storage) { return storage == LBM_FP64 ? 8 : 4; }
+
+constexpr int kDiagBlocks = 1024;
+
+int validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
+  if (!p->periodic_z && p->nz < 2) return fail(LBM_EINVAL, "walls need nz >= 2");
+  if ((double)p->nx * p->ny * p->nz >= 2147483648.0)
+    return fail(LBM_EINVAL, "lattice too large (N must be < 2^31)");
+  if (p->storage < LBM_FP64 || p->storage > LBM_BF16DEV) return fail(LBM_EINVAL, "unknown storage");
+  if (p->kernel != LBM_KERNEL_FUSED && p->kernel != LBM_KERNEL_REFERENCE &&
+      p->kernel != LBM_KERNEL_FUSED_RELOAD)
+    return fail(LBM_EINVAL, "unknown kernel");
+  if (p->tile_y != 0 && p->tile_y != 1 && p->tile_y != 2 && p->tile_y != 4 && p->tile_y != 8)
+    return fail(LBM_EINVAL, "tile_y must be 0, 1, 2, 4 or 8");
+  if (p->z_chunk < 0) return fail(LBM_EINVAL, "z_chunk must be >= 0");
+  if (!(p->tau_nu > 0.5) || !(p->tau_kappa > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2");
+  if (!(p->G <= 0.0) || !isfinite(p->G)) return fail(LBM_EINVAL, "G must be <= 0 and finite");
+  if (!(p->c_v > 0.0) || !(p->rho_kappa > 0.0)) return fail(LBM_EINVAL, "c_v and rho_kappa must be > 0");
+  if (!(p->T_d > 0.0) || !(p->T_u > 0.0)) return fail(LBM_EINVAL, "wall temperatures must be > 0");
+  if (!isfinite(p->gravity)) return fail(LBM_EINVAL, "gravity must be finite");
+  if (p->storage >= LBM_FP16DEV && (!(p->rho_ref > 0.0) || !(p->T_ref > 0.0)))
+    return fail(LBM_EINVAL, "16-bit storage needs rho_ref > 0 and T_ref > 0");
+  return LBM_OK;
+}
+
+struct Layout {
+  size_t N, pop_bytes, buf, scr, part, small, total;
+};
+
+Layout layout(const lbm_params* p) {
+  Layout L;
+  L.N = (size_t)p->nx * p->ny * p->nz;
+  L.pop_bytes = align_up(2 * Q * L.N * storage_bytes(p->storage));
+  L.buf = L.pop_bytes;
+  L.scr = align_up(L.N * real_bytes(p->storage));
+  L.part = align_up((size_t)kDiagBlocks * 8 * sizeof(double));
+  L.small = align_up((size_t)(16 + 4 * p->nz) * sizeof(double));
+  L.total = 2 * L.buf + 2 * L.scr + L.part + 2 * L.small;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_params p;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  void* buf[2];
+  void* srho;
+  void* sE;
+  double* partials;
+  double* small;   // totals / nusselt results
+  double* prof;    // plane profiles (2 nz)
+  int cur;
+  int64_t t;
+  int tile_y, z_chunk;
+};
+
+namespace {
+
+template <typename R>
+DevParams<R> dev_params(const lbm_params& p) {
+  DevParams<R> d;
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  d.periodic_z = p.periodic_z ? 1 : 0;
+  d.omega_f = (R)(1.0 / p.tau_nu);
+  d.omega_g = (R)(1.0 / p.tau_kappa);
+  d.tau_nu = (R)p.tau_nu;
+  d.G = (R)p.G;
+  d.gravity = (R)p.gravity;
+  d.inv_cv = (R)(1.0 / p.c_v);
+  d.gamma = (R)(1.0 + 1.0 / p.c_v);
+  d.rho_kappa = (R)p.rho_kappa;
+  d.T_d = (R)p.T_d;
+  d.T_u = (R)p.T_u;
+  const bool dev = p.storage >= LBM_FP16DEV;
+  for (int l = 0; l < Q; ++l) {
+    // reference populations: equilibrium at rest of (rho_ref, T_ref)
+    const double E = p.rho_ref * p.T_ref;
+    const double w = wlat<double>(l);
+    d.fref[l] = dev ? (R)(w * p.rho_ref) : R(0);
+    d.gref[l] = dev ? (R)(w * E + bg<double>(l) * (p.rho_kappa - p.rho_ref) * p.T_ref) : R(0);
+  }
+  return d;
+}
+
+int grid_for(size_t n, int block) {
+  size_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <typename C, bool KEEP>
+int launch_fused(lbm_handle* h, const void* in, void* out) {
+  using R = typename C::R;
+  const DevParams<R> P = dev_params<R>(h->p);
+  const int ty = h->tile_y;
+  const int ntx = (h->p.nx + 63) / 64, nty = (h->p.ny + ty - 1) / ty;
+  const int kz = h->z_chunk;
+  const int nzc = (h->p.nz + kz - 1) / kz;
+  const long long nblk = (long long)ntx * nty * nzc;
+  if (nblk > 0x7fffffffLL) return fail(LBM_EINVAL, "grid too large");
+  const auto* i = (const typename C::S*)in;
+  auto* o = (typename C::S*)out;
+  switch (ty) {
+    case 1: hipLaunchKernelGGL((k_fused<C, 1, KEEP>), dim3(nblk), dim3(64), 0, h->stream, i, o, P, ntx, nty, kz); break;
+    case 2: hipLaunchKernelGGL((k_fused<C, 2, KEEP>), dim3(nblk), dim3(128), 0, h->stream, i, o, P, ntx, nty, kz); break;
+    case 4: hipLaunchKernelGGL((k_fused<C, 4, KEEP>), dim3(nblk), dim3(256), 0, h->stream, i, o, P, ntx, nty, kz); break;
+    default: hipLaunchKernelGGL((k_fused<C, 8, KEEP>), dim3(nblk), dim3(512), 0, h->stream, i, o, P, ntx, nty, kz); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int launch_rhoE(lbm_handle* h, const void* in) {
+  using R = typename C::R;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_rhoE<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
+                     (const typename C::S*)in, (R*)h->srho, (R*)h->sE, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int launch_reference(lbm_handle* h, const void* in, void* out) {
+  using R = typename C::R;
+  int rc = launch_rhoE<C>(h, in);
+  if (rc) return rc;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_collide<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
+                     (const typename C::S*)in, (typename C::S*)out, (const R*)h->srho,
+                     (const R*)h->sE, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int do_step(lbm_handle* h) {
+  const void* in = h->buf[h->cur];
+  void* out = h->buf[1 - h->cur];
+  int rc;
+  switch (h->p.kernel) {
+    case LBM_KERNEL_FUSED: rc = launch_fused<C, true>(h, in, out); break;
+    case LBM_KERNEL_FUSED_RELOAD: rc = launch_fused<C, false>(h, in, out); break;
+    default: rc = launch_reference<C>(h, in, out); break;
+  }
+  if (rc) return rc;
+  h->cur = 1 - h->cur;
+  h->t += 1;
+  return LBM_OK;
+}
+
+template <typename C>
+int do_init(lbm_handle* h, const double* rho0, const double* T0) {
+  using R = typename C::R;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_init<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
+                     (typename C::S*)h->buf[0], rho0, T0, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int do_get(lbm_handle* h, double* st) {
+  using R = typename C::R;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_get_state<C>), dim3(grid_for(2 * Q * h->L.N, 256)), dim3(256), 0,
+                     h->stream, (const typename C::S*)h->buf[h->cur], st, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int do_set(lbm_handle* h, const double* st) {
+  using R = typename C::R;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_set_state<C>), dim3(grid_for(2 * Q * h->L.N, 256)), dim3(256), 0,
+                     h->stream, (typename C::S*)h->buf[h->cur], st, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename C>
+int do_moments(lbm_handle* h, double* totals, double* fields) {
+  using R = typename C::R;
+  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  if (rc) return rc;
+  const DevParams<R> P = dev_params<R>(h->p);
+  const int nblk = std::min(kDiagBlocks, grid_for(h->L.N, 256));
+  hipLaunchKernelGGL((k_diag<C>), dim3(nblk), dim3(256), 0, h->stream,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
+                     h->p.c_v, h->p.G, fields, h->partials);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
+  HIP_TRY(hipGetLastError());
+  double out[7];
+  HIP_TRY(hipMemcpyAsync(out, h->small, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (totals)
+    for (int q = 0; q < 6; ++q) totals[q] = out[q];
+  if (out[6] != 0.0) return fail(LBM_ENUMERIC, "non-finite value or rho <= 0 in the state");
+  return LBM_OK;
+}
+
+template <typename C>
+int do_nusselt(lbm_handle* h, double* nb, double* nt, double* nu_z, double* T_z) {
+  using R = typename C::R;
+  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  if (rc) return rc;
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_plane<C>), dim3(h->p.nz), dim3(256), 0, h->stream,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
+                     h->p.c_v, h->p.G, h->prof);
+  HIP_TRY(hipGetLastError());
+  const double kappa = h->p.c_v * (h->p.tau_kappa - 0.5) * h->p.rho_kappa / 3.0;
+  hipLaunchKernelGGL(k_finish_nusselt, dim3(1), dim3(256), 0, h->stream, h->prof, h->p.nz,
+                     h->p.T_d, h->p.T_u, kappa, h->small);
+  HIP_TRY(hipGetLastError());
+  const int nz = h->p.nz;
+  double* host = (double*)malloc(sizeof(double) * (2 + 2 * (size_t)nz));
+  if (!host) return fail(LBM_EINVAL, "host allocation failed");
+  hipError_t e = hipMemcpyAsync(host, h->small, sizeof(double) * (2 + 2 * (size_t)nz),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    free(host);
+    return fail(LBM_EHIP, std::string("nusselt copy: ") + hipGetErrorString(e));
+  }
+  if (nb) *nb = host[0];
+  if (nt) *nt = host[1];
+  if (nu_z) memcpy(nu_z, host + 2, sizeof(double) * nz);
+  if (T_z) memcpy(T_z, host + 2 + nz, sizeof(double) * nz);
+  free(host);
+  return LBM_OK;
+}
+
+template <template <typename> class Fn, typename... A>
+int dispatch(int storage, A... a) {
+  switch (storage) {
+    case LBM_FP64: return Fn<F64>::run(a...);
+    case LBM_FP32: return Fn<F32>::run(a...);
+    case LBM_FP16DEV: return Fn<H16>::run(a...);
+    default: return Fn<B16>::run(a...);
+  }
+}
+template <typename C> struct StepFn { static int run(lbm_handle* h) { return do_step<C>(h); } };
+template <typename C> struct InitFn {
+  static int run(lbm_handle* h, const double* r, const double* T) { return do_init<C>(h, r, T); }
+};
+template <typename C> struct GetFn { static int run(lbm_handle* h, double* s) { return do_get<C>(h, s); } };
+template <typename C> struct SetFn {
+  static int run(lbm_handle* h, const double* s) { return do_set<C>(h, s); }
+};
+template <typename C> struct MomFn {
+  static int run(lbm_handle* h, double* t, double* f) { return do_moments<C>(h, t, f); }
+};
+template <typename C> struct NuFn {
+  static int run(lbm_handle* h, double* a, double* b, double* c, double* d) {
+    return do_nusselt<C>(h, a, b, c, d);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_version(void) { return "paper_1111_0905_amd lbm 0.1 (gfx950)"; }
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  return layout(p).total;
+}
+
+int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const double* rho0,
+             const double* T0, void* stream, lbm_handle** out) {
+  g_err.clear();
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!rho0) return fail(LBM_EINVAL, "rho0 is NULL");
+  const Layout L = layout(p);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(LBM_EWORKSPACE, "workspace smaller than lbm_workspace_bytes()");
+  if (((uintptr_t)workspace) % kAlign)
+    return fail(LBM_EWORKSPACE, "workspace must be 256-byte aligned");
+  lbm_handle* h = new (std::nothrow) lbm_handle();
+  if (!h) return fail(LBM_EINVAL, "host allocation failed");
+  h->p = *p;
+  h->L = L;
+  h->stream = (hipStream_t)stream;
+  h->ws = (char*)workspace;
+  char* c = h->ws;
+  h->buf[0] = c; c += L.buf;
+  h->buf[1] = c; c += L.buf;
+  h->srho = c; c += L.scr;
+  h->sE = c; c += L.scr;
+  h->partials = (double*)c; c += L.part;
+  h->small = (double*)c; c += L.small;
+  h->prof = (double*)c;
+  h->cur = 0;
+  h->t = 0;
+  // defaults from a tile/chunk sweep at 512^3 on MI355X
+  h->tile_y = p->tile_y ? p->tile_y : (p->storage == LBM_FP64 ? 2 : 8);
+  h->z_chunk = p->z_chunk ? std::min(p->z_chunk, p->nz) : std::min(128, p->nz);
+  rc = dispatch<InitFn>(p->storage, h, rho0, T0);
+  if (rc == LBM_OK) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = fail(LBM_EHIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t n) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (int64_t s = 0; s < n; ++s) {
+    const int rc = dispatch<StepFn>(h->p.storage, h);
+    if (rc) return rc;
+  }
+  return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_handle* h) { return h ? h->t : -1; }
+
+int lbm_moments(lbm_handle* h, double* totals, double* fields) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  return dispatch<MomFn>(h->p.storage, h, totals, fields);
+}
+
+int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, double* T_z) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (h->p.periodic_z) return fail(LBM_EINVAL, "Nusselt numbers need walls");
+  if (!(h->p.T_d != h->p.T_u)) return fail(LBM_EINVAL, "Nusselt numbers need T_d != T_u");
+  return dispatch<NuFn>(h->p.storage, h, nu_bot, nu_top, nu_z, T_z);
+}
+
+int lbm_get_state(lbm_handle* h, double* state) {
+  if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
+  return dispatch<GetFn>(h->p.storage, h, state);
+}
+
+int lbm_set_state(lbm_handle* h, const double* state) {
+  if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
+  const int rc = dispatch<SetFn>(h->p.storage, h, state);
+  if (rc == LBM_OK) h->t = 0;
+  return rc;
+}
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// physics.hpp - per-node arithmetic of the thermal pseudopotential D3Q19 step
+// for gfx950, shared by every kernel of the library (reference, fused and
+// diagnostics) so that they all compute bit-identical node updates.
+//
+// The scheme (arXiv:1111.0905, section "Algorithm"):
+//   eq. (HYDRO)  rho = sum f, j = sum c f, E = rho T = sum g;
+//   eq. (FORCE)  F_SC = -G psi(x) sum_l W_l c_l psi(x + c_l), psi = exp(-1/rho),
+//                W = 1/6 (axis), 1/12 (face diagonal): isotropic to 4th order;
+//   f/g coupling: F_T = -grad(rho T - rho/3) puts the ideal pressure rho T
+//                 (T from the g populations) into the momentum equation;
+//   gravity:      F_g = rho (0, 0, -g)  (eq. (ns));
+//   velocity shift u' = (j + tau_nu F)/rho inside f^eq; physical v = (j + F/2)/rho;
+//   eqs. (LBEQ)/(LBEQ2) BGK with
+//     f^eq_l = w_l rho [1 + 3 c.u' + 4.5 (c.u')^2 - 1.5 u'^2],
+//     g^eq_l = w_l [E + gamma E (3 c.v + 4.5 (c.v)^2 - 1.5 v^2)] + b_l (rho_kappa - rho) T,
+//       gamma = 1 + 1/c_v, b_0 = -2/3, b_l = w_l: one conductivity
+//       kappa = c_v (tau_kappa - 1/2) rho_kappa / 3 in both phases;
+//   counter-term of the g dynamics: the factor gamma plus the source
+//     S = (1/c_v) v . grad E added as w_l S, so that
+//     dE/dt + div(E v) = -(E/c_v) div v + (kappa/c_v) lap T (eq. (eq), 2nd form).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+// D3Q19 velocity set (same order as the canonical state of the C ABI).
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+template <typename R>
+__host__ __device__ constexpr R wlat(int l) {
+  return l == 0 ? R(1) / R(3) : (l < 7 ? R(1) / R(18) : R(1) / R(36));
+}
+// isotropic second-moment adjuster of g^eq
+template <typename R>
+__host__ __device__ constexpr R bg(int l) {
+  return l == 0 ? R(-2) / R(3) : wlat<R>(l);
+}
+
+// Device-side parameters in compute precision.
+template <typename R>
+struct DevParams {
+  int nx, ny, nz;
+  int periodic_z;
+  R omega_f, omega_g;   // 1/tau_nu, 1/tau_kappa
+  R tau_nu;
+  R G;
+  R gravity;
+  R inv_cv, gamma;      // 1/c_v, 1 + 1/c_v
+  R rho_kappa;
+  R T_d, T_u;
+  R fref[Q], gref[Q];   // deviation references (16-bit storage only)
+};
+
+// ----------------------------------------------------------- storage codecs
+// Populations are stored as S and computed in R.  The 16-bit forms store
+// (pop - pop_ref) and round to nearest even.
+struct F64 { using S = double; using R = double; };
+struct F32 { using S = float; using R = float; };
+struct H16 { using S = uint16_t; using R = float; };
+struct B16 { using S = uint16_t; using R = float; };
+
+template <typename C> struct Codec;
+// p is a (wave-uniform) population base pointer, i a 32-bit node offset, so
+// that loads and stores use the scalar-base + 32-bit vector-offset form.
+template <> struct Codec<F64> {
+  static __device__ __forceinline__ double ld(const double* p, uint32_t i, double) { return p[i]; }
+  static __device__ __forceinline__ void st(double* p, uint32_t i, double v, double) { p[i] = v; }
+};
+template <> struct Codec<F32> {
+  static __device__ __forceinline__ float ld(const float* p, uint32_t i, float) { return p[i]; }
+  static __device__ __forceinline__ void st(float* p, uint32_t i, float v, float) { p[i] = v; }
+};
+template <> struct Codec<H16> {
+  static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
+    return (float)__builtin_bit_cast(_Float16, p[i]) + ref;
+  }
+  static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
+    p[i] = __builtin_bit_cast(uint16_t, (_Float16)(v - ref));
+  }
+};
+template <> struct Codec<B16> {
+  static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
+    return __builtin_bit_cast(float, (uint32_t)p[i] << 16) + ref;
+  }
+  static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
+    uint32_t u = __builtin_bit_cast(uint32_t, v - ref);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+    p[i] = (uint16_t)(u >> 16);
+  }
+};
+
+// ----------------------------------------------------------- node arithmetic
+
+template <typename R>
+__device__ __forceinline__ R psi_of(R rho) { return exp(R(-1) / rho); }
+
+// W-stencil central gradient sum_l W_l c_l a(x + c_l); at(l) returns the
+// neighbour value in direction l.
+template <typename R, typename A>
+__device__ __forceinline__ void grad_w(const A& at, R& gx, R& gy, R& gz) {
+  const R a1 = at(1), a2 = at(2), a3 = at(3), a4 = at(4), a5 = at(5), a6 = at(6);
+  const R a7 = at(7), a8 = at(8), a9 = at(9), a10 = at(10), a11 = at(11), a12 = at(12);
+  const R a13 = at(13), a14 = at(14), a15 = at(15), a16 = at(16), a17 = at(17), a18 = at(18);
+  const R s6 = R(1) / R(6), s12 = R(1) / R(12);
+  gx = s6 * (a1 - a2) + s12 * (((a7 - a8) + (a9 - a10)) + ((a11 - a12) + (a13 - a14)));
+  gy = s6 * (a3 - a4) + s12 * (((a7 - a8) - (a9 - a10)) + ((a15 - a16) + (a17 - a18)));
+  gz = s6 * (a5 - a6) + s12 * (((a11 - a12) - (a13 - a14)) + ((a15 - a16) - (a17 - a18)));
+}
+
+template <typename R>
+struct Macro {
+  R rho, E, T, psi;
+  R jx, jy, jz;
+  R Fx, Fy, Fz;
+  R vx, vy, vz;   // physical velocity (j + F/2)/rho
+  R S;            // counter-term source (1/c_v) v . grad E
+};
+
+template <typename R>
+__device__ __forceinline__ void moments(const R* f, const R* g, R& rho, R& E) {
+  R r = R(0), e = R(0);
+#pragma unroll
+  for (int l = 0; l < Q; ++l) { r += f[l]; e += g[l]; }
+  rho = r;
+  E = e;
+}
+
+// Node-local macroscopic quantities from the node's populations and the
+// three neighbour gradients (psi, E, rho).
+template <typename R>
+__device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R E, R psi,
+                                               R gpx, R gpy, R gpz, R gEx, R gEy, R gEz,
+                                               R grx, R gry, R grz, const DevParams<R>& P) {
+  Macro<R> m;
+  m.rho = rho;
+  m.E = E;
+  m.psi = psi;
+  m.T = E / rho;
+  m.jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
+  m.jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
+  m.jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+  const R third = R(1) / R(3);
+  const R gp = -P.G * psi;
+  m.Fx = gp * gpx - (gEx - third * grx);
+  m.Fy = gp * gpy - (gEy - third * gry);
+  m.Fz = gp * gpz - (gEz - third * grz) - P.gravity * rho;
+  const R ir = R(1) / rho;
+  m.vx = (m.jx + R(0.5) * m.Fx) * ir;
+  m.vy = (m.jy + R(0.5) * m.Fy) * ir;
+  m.vz = (m.jz + R(0.5) * m.Fz) * ir;
+  m.S = (m.vx * gEx + m.vy * gEy + m.vz * gEz) * P.inv_cv;
+  return m;
+}
+
+// BGK collision of both populations at one node (eqs. (LBEQ)/(LBEQ2) right
+// hand sides plus the counter-term); emit(l, f*_l, g*_l) receives the
+// post-collision values.
+template <typename R, typename Emit>
+__device__ __forceinline__ void collide(const R* f, const R* g, const Macro<R>& m,
+                                        const DevParams<R>& P, Emit&& emit) {
+  const R ir = R(1) / m.rho;
+  const R ux = (m.jx + P.tau_nu * m.Fx) * ir;
+  const R uy = (m.jy + P.tau_nu * m.Fy) * ir;
+  const R uz = (m.jz + P.tau_nu * m.Fz) * ir;
+  const R uu = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R vv = R(-1.5) * (m.vx * m.vx + m.vy * m.vy + m.vz * m.vz);
+  const R gE = P.gamma * m.E;
+  const R rk = (P.rho_kappa - m.rho) * m.T;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    const R cu = R(CX[l]) * ux + R(CY[l]) * uy + R(CZ[l]) * uz;
+    const R cv = R(CX[l]) * m.vx + R(CY[l]) * m.vy + R(CZ[l]) * m.vz;
+    const R w = wlat<R>(l);
+    const R feq = w * m.rho * (uu + cu * (R(3) + R(4.5) * cu));
+    const R geq = w * (m.E + gE * (vv + cv * (R(3) + R(4.5) * cv))) + bg<R>(l) * rk;
+    const R fs = f[l] - P.omega_f * (f[l] - feq);
+    const R gs = g[l] - P.omega_g * (g[l] - geq) + w * m.S;
+    emit(l, fs, gs);
+  }
+}
+
+// Local equilibrium at rest (initial state).
+template <typename R>
+__device__ __forceinline__ void rest_equilibrium(R rho, R T, const DevParams<R>& P, R* f, R* g) {
+  const R E = rho * T;
+  const R rk = (P.rho_kappa - rho) * T;
+#pragma unroll
+  for (int l = 0; l < Q; ++l) {
+    f[l] = wlat<R>(l) * rho;
+    g[l] = wlat<R>(l) * E + bg<R>(l) * rk;
+  }
+}
+
+}  // namespace lbm

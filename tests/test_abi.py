@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every entry point include/lbm.h
+declares; host-side parameter validation works without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1111_0905_amd import lbm
+    return lbm.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ["lbm_init", "lbm_step", "lbm_moments", "lbm_nusselt", "lbm_get_state",
+                 "lbm_set_state", "lbm_workspace_bytes", "lbm_destroy", "lbm_last_error"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.lbm_version()
+
+
+def test_workspace_bytes_and_validation(lib):
+    from paper_1111_0905_amd import lbm
+    p = lbm.Params(64, 32, 16, storage=lbm.LBM_FP32)
+    n = p.n
+    nb = lbm.lbm_workspace_bytes(p)
+    assert nb >= 2 * 38 * n * 4 + 2 * n * 4
+    p64 = lbm.Params(64, 32, 16, storage=lbm.LBM_FP64)
+    assert lbm.lbm_workspace_bytes(p64) > nb
+    p16 = lbm.Params(64, 32, 16, storage=lbm.LBM_FP16DEV)
+    assert lbm.lbm_workspace_bytes(p16) < nb
+    for bad in [dict(nx=0), dict(tau_nu=0.5), dict(tau_kappa=0.3), dict(G=0.1), dict(T_d=0.0),
+                dict(nz=1), dict(storage=7), dict(kernel=9), dict(c_v=0.0), dict(tile_y=3),
+                dict(storage=lbm.LBM_FP16DEV, rho_ref=0.0)]:
+        q = lbm.Params(8, 8, 8)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_workspace_bytes(q)
+    # one plane is fine without walls
+    assert lbm.lbm_workspace_bytes(lbm.Params(8, 8, 1, periodic_z=1)) > 0
+
+
+def test_null_handle_is_rejected(lib):
+    assert lib.lbm_step(None, 1) == -1
+    assert b"NULL" in lib.lbm_last_error()

@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars:
+* FP64 storage and arithmetic: max |state_gpu - state_oracle| / max |state|
+  <= 1e-12 after the given steps (rounding order differs only);
+* FP32: relative error of the moment fields (rho, v, T) <= 1e-5 after 100
+  steps (field-scale metric, see fp32_tolerance below);
+* every kernel variant (fused, fused-reload, reference; tile heights;
+  z-chunking) gives the same FP64 results up to the compiler's contraction
+  of multiply-adds (1e-14 relative).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import eos
+from oracle import lbm as olbm
+
+pytestmark = pytest.mark.gpu
+
+TC = 0.05
+G = eos.coupling_for_tc(TC)
+
+
+@pytest.fixture(scope="module")
+def glbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1111_0905_amd import lbm
+    lbm.load_library()
+    return lbm
+
+
+def _kw(**over):
+    kw = dict(tau_nu=1.0, tau_kappa=1.0, G=G, T_d=0.95 * TC, T_u=0.85 * TC, gravity=1e-5)
+    kw.update(over)
+    return kw
+
+
+def _mean_density():
+    rg, rl, _ = eos.maxwell(0.9 * TC, G)
+    return 0.5 * (rg + rl)
+
+
+def _oracle_state(nx, ny, nz, rho0, steps, **kw):
+    periodic = kw.pop("periodic_z", 0)
+    o = olbm.Oracle(olbm.Params(nx, ny, nz, periodic_z=bool(periodic), **kw), rho0)
+    o.step(steps)
+    return o
+
+
+def _gpu(glbm, nx, ny, nz, rho0, steps, storage, **kw):
+    p = glbm.Params(nx, ny, nz, storage=storage, **kw)
+    lat = glbm.Lattice(p, torch.from_numpy(np.ascontiguousarray(rho0)).cuda())
+    lat.step(steps)
+    torch.cuda.synchronize()
+    return lat
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_config1_fp64_fused_matches_oracle(glbm):
+    """32^3, 100 steps, spinodal mean density, walls, gravity."""
+    n = 32
+    print(f"case: 32^3 FP64 fused 100 steps", flush=True)
+    rho0 = synth.noisy_density(n, n, n, _mean_density(), 0.01, 1234)
+    o = _oracle_state(n, n, n, rho0, 100, **_kw())
+    lat = _gpu(glbm, n, n, n, rho0, 100, glbm.LBM_FP64, **_kw())
+    err = _rel(lat.state().cpu().numpy(), o.state().numpy())
+    print(f"max rel state err {err:.3e}")
+    assert err < 1e-12
+    tot = lat.moments()
+    want = o.moments().numpy()
+    assert abs(tot[0] / want[0] - 1) < 1e-13
+    assert np.allclose(tot[4:], want[4:], rtol=1e-12, atol=0)
+    # momentum: compare on the scale of sum |rho v|
+    scale = float((o.fields()["rho"] * o.fields()["v"].abs()).sum())
+    assert np.abs(tot[1:4] - want[1:4]).max() < 1e-11 * scale
+    nb, nt, nu_z, T_z = lat.nusselt()
+    onb, ont, onu, oT = o.nusselt()
+    assert abs(nb - float(onb)) < 1e-9 * max(1, abs(float(onb)))
+    assert abs(nt - float(ont)) < 1e-9 * max(1, abs(float(ont)))
+    assert np.allclose(nu_z, onu.numpy(), rtol=1e-9, atol=1e-9)
+    assert np.allclose(T_z, oT.numpy(), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("shape", [(20, 12, 9), (1, 1, 5), (70, 3, 2), (65, 9, 130)])
+@pytest.mark.parametrize("periodic", [0, 1])
+def test_ragged_shapes_fp64(glbm, shape, periodic):
+    nx, ny, nz = shape
+    print(f"case: ragged {shape} periodic={periodic}", flush=True)
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 7)
+    kw = _kw(tau_nu=0.8, tau_kappa=0.7, gravity=1e-4)
+    steps = 6
+    o = _oracle_state(nx, ny, nz, rho0, steps, periodic_z=periodic, **kw)
+    lat = _gpu(glbm, nx, ny, nz, rho0, steps, glbm.LBM_FP64, periodic_z=periodic, **kw)
+    err = _rel(lat.state().cpu().numpy(), o.state().numpy())
+    assert err < 1e-12, err
+
+
+def test_kernel_variants_agree_fp64(glbm):
+    nx, ny, nz = 70, 19, 23
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 11)
+    kw = _kw(tau_nu=0.7, tau_kappa=0.9, gravity=1e-4)
+    ref = None
+    for kernel, ty, zc in [(1, 0, 0), (0, 1, 0), (0, 2, 0), (0, 4, 0), (0, 8, 0), (0, 2, 5),
+                           (2, 4, 7), (2, 8, 0)]:
+        print(f"case: variant kernel={kernel} tile_y={ty} z_chunk={zc}", flush=True)
+        lat = _gpu(glbm, nx, ny, nz, rho0, 5, glbm.LBM_FP64, kernel=kernel, tile_y=ty,
+                   z_chunk=zc, **kw)
+        s = lat.state().cpu().numpy()
+        if ref is None:
+            ref = s
+        else:
+            assert _rel(s, ref) < 1e-14, (kernel, ty, zc, _rel(s, ref))
+
+
+def fp32_tolerance():
+    return 1e-5
+
+
+def test_config1_fp32_fields_match_oracle(glbm):
+    n = 32
+    print("case: 32^3 FP32 fused 100 steps", flush=True)
+    rho0 = synth.noisy_density(n, n, n, _mean_density(), 0.01, 1234)
+    o = _oracle_state(n, n, n, rho0, 100, **_kw())
+    lat = _gpu(glbm, n, n, n, rho0, 100, glbm.LBM_FP32, **_kw())
+    _, fl = lat.fields()
+    fl = fl.cpu().numpy()
+    of = o.fields()
+    rho = of["rho"].numpy()
+    v = of["v"].numpy()
+    T = of["T"].numpy()
+    e_rho = _rel(fl[0], rho)
+    e_v = float(np.abs(fl[1:4] - v).max() / np.abs(v).max())
+    e_T = _rel(fl[4], T)
+    print(f"FP32 errors: rho {e_rho:.2e} v {e_v:.2e} T {e_T:.2e}")
+    assert e_rho < fp32_tolerance() and e_T < fp32_tolerance()
+    assert e_v < 10 * fp32_tolerance()
+
+
+def test_state_roundtrip_and_time(glbm):
+    nx, ny, nz = 16, 8, 6
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 3)
+    lat = _gpu(glbm, nx, ny, nz, rho0, 3, glbm.LBM_FP64, **_kw())
+    assert lat.t == 3
+    s = lat.state().clone()
+    lat.step(2)
+    lat.set_state(s)
+    assert lat.t == 0
+    assert torch.equal(lat.state(), s)
+
+
+def test_checkpoint_resume_is_bit_identical(glbm):
+    nx, ny, nz = 24, 10, 12
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 5)
+    a = _gpu(glbm, nx, ny, nz, rho0, 10, glbm.LBM_FP32, **_kw())
+    b = _gpu(glbm, nx, ny, nz, rho0, 4, glbm.LBM_FP32, **_kw())
+    ck = b.state().clone()
+    del b
+    c = _gpu(glbm, nx, ny, nz, rho0, 0, glbm.LBM_FP32, **_kw())
+    c.set_state(ck)
+    c.step(6)
+    assert torch.equal(a.state(), c.state())
+
+
+def test_invalid_rho_reports_numeric_error(glbm):
+    nx, ny, nz = 8, 8, 4
+    rho0 = np.full((nz, ny, nx), 1.5)
+    lat = _gpu(glbm, nx, ny, nz, rho0, 0, glbm.LBM_FP32, **_kw())
+    s = lat.state()
+    s[:, 2, 3, 4] = float("nan")
+    lat.set_state(s)
+    with pytest.raises(glbm.LbmError) as e:
+        lat.moments()
+    assert e.value.code == -4
