@@ -34,9 +34,10 @@ RHO_BOIL = 1.93                        # liquid-rich mean density, boils at the 
 GRAVITY = 3.2e-6
 
 
-def workload_params(lbm, n, storage, kernel=0, tile_y=0, z_chunk=0):
+def workload_params(lbm, n, storage, kernel=0, tile_y=0, z_chunk=0, tile_x=0):
     return lbm.Params(
-        n, n, n, storage=lbm.STORAGE[storage], kernel=kernel, tile_y=tile_y, z_chunk=z_chunk,
+        n, n, n, storage=lbm.STORAGE[storage], kernel=kernel, tile_x=tile_x, tile_y=tile_y,
+        z_chunk=z_chunk,
         tau_nu=TAU_NU, tau_kappa=TAU_KAPPA, G=-TC * math.e ** 2, T_d=0.95 * TC, T_u=0.85 * TC,
         gravity=GRAVITY, c_v=1.0, rho_kappa=0.5, rho_ref=RHO_BOIL, T_ref=0.9 * TC)
 
@@ -57,9 +58,9 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def run_storage(lbm, n, storage, steps, warmup, rho0, kernel=0, tile_y=0, z_chunk=0):
+def run_storage(lbm, n, storage, steps, warmup, rho0, kernel=0, tile_y=0, z_chunk=0, tile_x=0):
     import torch
-    p = workload_params(lbm, n, storage, kernel, tile_y, z_chunk)
+    p = workload_params(lbm, n, storage, kernel, tile_y, z_chunk, tile_x)
     lat = lbm.Lattice(p, rho0)
     ms, wall = time_steps(lat, steps, warmup)
     tot = lat.moments()          # also checks the state is finite
@@ -107,13 +108,36 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--kernel", type=int, default=0)
+    ap.add_argument("--tile-x", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--z-chunk", type=int, default=0)
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--no-16bit", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="time kernel/tile variants")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        nbytes = 2 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 10
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_each_way": nbytes, "ms": round(ms, 4),
+                          "gbs_read_plus_write": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -130,19 +154,18 @@ def main():
     rho0 = torch.from_numpy(synth.noisy_density(n, n, n, RHO_BOIL, 0.01, 1234)).cuda().reshape(-1)
 
     if args.sweep:
-        for kernel in (0, 2):
-            for ty in (1, 2, 4, 8):
-                for zc in (0, 128, 512):
-                    r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
-                                       kernel, ty, zc)
-                    print(json.dumps({"kernel": kernel, "tile_y": ty, "z_chunk": zc,
-                                      "ms": round(r["ms_per_step"], 4),
-                                      "mlups": round(r["mlups"], 1),
-                                      "gbs": round(r["achieved_gbs"], 1)}), flush=True)
+        combos = [(0, 64, 8), (2, 64, 8), (2, 64, 16), (0, 32, 16), (2, 32, 16), (2, 32, 32)]
+        for kernel, tx, ty in combos:
+            for zc in (128, 512):
+                r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
+                                   kernel, ty, zc, tx)
+                print(json.dumps({"kernel": kernel, "tile": [tx, ty], "z_chunk": zc,
+                                  "ms": round(r["ms_per_step"], 4), "mlups": round(r["mlups"], 1),
+                                  "gbs": round(r["achieved_gbs"], 1)}), flush=True)
         return
 
     main_res, tot = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
-                                args.kernel, args.tile_y, args.z_chunk)
+                                args.kernel, args.tile_y, args.z_chunk, args.tile_x)
     print(f"bench: {args.storage} {main_res['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     extra = {}
     if not args.no_16bit:

@@ -90,14 +90,17 @@ enum {
  *   rho_ref, T_ref: reference state of the FP16/BF16 deviation storage
  *     (pop_ref = equilibrium at rest of (rho_ref, T_ref)); ignored otherwise.
  *   periodic_z: 0 = walls (nz >= 2), 1 = periodic in z as well.
- *   kernel: LBM_KERNEL_*; tile_y: rows per fused-kernel tile (0 = default).
+ *   kernel: LBM_KERNEL_*.
+ *   tile_x x tile_y: x-y tile of one fused-kernel work-group; supported
+ *     64 x {1, 2, 4, 8, 16} and 32 x {8, 16, 32}; 0 picks the default.
  */
 typedef struct lbm_params {
   int32_t nx, ny, nz;
   int32_t storage;
   int32_t periodic_z;
   int32_t kernel;
-  int32_t tile_y;
+  int32_t tile_x;      /* fused-kernel tile width: 0 (default 64), 32 or 64 */
+  int32_t tile_y;      /* fused-kernel tile height: 0 (default), 1..32, see lbm_init */
   int32_t z_chunk;     /* planes per fused-kernel work-group column (0 = default) */
   double tau_nu, tau_kappa;
   double G;

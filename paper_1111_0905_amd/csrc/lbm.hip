@@ -66,24 +66,25 @@ struct Streamer {
   __device__ __forceinline__ void operator()(int l, R fs, R gs) const {
     const int nz = P.nz;
     int kk = k + CZ[l];
-    int ii = CX[l] > 0 ? ip : (CX[l] < 0 ? im : i);
-    int jj = CY[l] > 0 ? jp : (CY[l] < 0 ? jm : j);
-    int q = l;
-    if (kk < 0 || kk >= nz) {
-      if (P.periodic_z) {
-        kk = kk < 0 ? kk + nz : kk - nz;
-      } else {  // the wall sends it back into this node in the opposite direction
-        const R Tw = kk < 0 ? P.T_d : P.T_u;
-        q = OPP[l];
-        ii = i;
-        jj = j;
-        kk = k;
-        gs = -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw;
-      }
+    const int ii = CX[l] > 0 ? ip : (CX[l] < 0 ? im : i);
+    const int jj = CY[l] > 0 ? jp : (CY[l] < 0 ? jm : j);
+    if (kk >= 0 && kk < nz) {
+      const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
+      Codec<C>::st(out + (size_t)l * N, o, fs, P.fref[l]);
+      Codec<C>::st(out + (size_t)(l + Q) * N, o, gs, P.gref[l]);
+    } else if (P.periodic_z) {
+      kk = kk < 0 ? kk + nz : kk - nz;
+      const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
+      Codec<C>::st(out + (size_t)l * N, o, fs, P.fref[l]);
+      Codec<C>::st(out + (size_t)(l + Q) * N, o, gs, P.gref[l]);
+    } else {  // the wall sends it back into this node in the opposite direction
+      const R Tw = kk < 0 ? P.T_d : P.T_u;
+      const int q = OPP[l];
+      const uint32_t o = node_off(i, j, k, P.nx, P.ny);
+      Codec<C>::st(out + (size_t)q * N, o, fs, P.fref[OPP[l]]);
+      Codec<C>::st(out + (size_t)(q + Q) * N, o, -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw,
+                   P.gref[OPP[l]]);
     }
-    const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
-    Codec<C>::st(out + (size_t)q * N, o, fs, P.fref[q]);
-    Codec<C>::st(out + (size_t)(q + Q) * N, o, gs, P.gref[q]);
   }
 };
 
@@ -126,24 +127,29 @@ template <typename C, typename R = typename C::R>
 __global__ void k_get_state(const typename C::S* __restrict__ in, double* __restrict__ st,
                             DevParams<R> P) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
-  const size_t M = (size_t)2 * Q * N;
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < M;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
-    const int q = (int)(n / N);
-    st[n] = (double)Codec<C>::ld(in + (size_t)q * N, (uint32_t)(n - (size_t)q * N),
-                                 q < Q ? P.fref[q] : P.gref[q - Q]);
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      st[(size_t)l * N + n] = (double)f[l];
+      st[(size_t)(l + Q) * N + n] = (double)g[l];
+    }
   }
 }
 
 template <typename C, typename R = typename C::R>
 __global__ void k_set_state(typename C::S* out, const double* __restrict__ st, DevParams<R> P) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
-  const size_t M = (size_t)2 * Q * N;
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < M;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
-    const int q = (int)(n / N);
-    Codec<C>::st(out + (size_t)q * N, (uint32_t)(n - (size_t)q * N), (R)st[n],
-                 q < Q ? P.fref[q] : P.gref[q - Q]);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, (R)st[(size_t)l * N + n], P.fref[l]);
+      Codec<C>::st(out + (size_t)(l + Q) * N, (uint32_t)n, (R)st[(size_t)(l + Q) * N + n],
+                   P.gref[l]);
+    }
   }
 }
 
@@ -230,15 +236,15 @@ __global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* _
 
 // ---------------------------------------------------------------- fused path
 
-// One work-group: tile of 64 x TY nodes in x-y, planes [k0, k1) in z.
+// One work-group: tile of TX x TY nodes in x-y, planes [k0, k1) in z.
 // LDS ring buffer of three planes of psi, rho and E over the tile plus a
 // one-node ring; the populations of the plane being collided and of the next
 // plane are held in registers, so each population is read once from HBM.
-template <typename C, int TY, bool KEEP, typename R = typename C::R>
-__global__ __launch_bounds__(64 * TY) void k_fused(const typename C::S* __restrict__ in,
+template <typename C, int TX, int TY, bool KEEP, typename R = typename C::R>
+__global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restrict__ in,
                                                   typename C::S* __restrict__ out,
                                                   DevParams<R> P, int ntx, int nty, int kz) {
-  constexpr int TX = 64, PW = TX + 2, PN = PW * (TY + 2);
+  constexpr int PW = TX + 2, PN = PW * (TY + 2);
   __shared__ R sPsi[3][PN];
   __shared__ R sRho[3][PN];
   __shared__ R sE[3][PN];
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(64 * TY) void k_fused(const typename C::S* __restri
 
   // the one-node ring around the tile: 2 (tw + 2) + 2 th nodes, dealt to the
   // threads in turn
-  constexpr int NT = 64 * TY;
+  constexpr int NT = TX * TY;
   const int nring = 2 * (tw + 2) + 2 * th;
   auto ring_xy = [&](int r, int& rx, int& ry) {
     if (r < tw + 2) {
@@ -514,14 +520,20 @@ int validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
   if (!p->periodic_z && p->nz < 2) return fail(LBM_EINVAL, "walls need nz >= 2");
-  if ((double)p->nx * p->ny * p->nz >= 2147483648.0)
-    return fail(LBM_EINVAL, "lattice too large (N must be < 2^31)");
+  if ((double)p->nx * p->ny * p->nz * (p->storage == LBM_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+    return fail(LBM_EINVAL, "lattice too large (one population array must stay below 4 GiB)");
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16DEV) return fail(LBM_EINVAL, "unknown storage");
   if (p->kernel != LBM_KERNEL_FUSED && p->kernel != LBM_KERNEL_REFERENCE &&
       p->kernel != LBM_KERNEL_FUSED_RELOAD)
     return fail(LBM_EINVAL, "unknown kernel");
-  if (p->tile_y != 0 && p->tile_y != 1 && p->tile_y != 2 && p->tile_y != 4 && p->tile_y != 8)
-    return fail(LBM_EINVAL, "tile_y must be 0, 1, 2, 4 or 8");
+  {
+    const int tx = p->tile_x, ty = p->tile_y;
+    const bool ok = (tx == 0 && ty == 0) ||
+                    (tx == 64 && (ty == 1 || ty == 2 || ty == 4 || ty == 8 || ty == 16)) ||
+                    (tx == 32 && (ty == 8 || ty == 16 || ty == 32)) ||
+                    (tx == 0 && (ty == 1 || ty == 2 || ty == 4 || ty == 8 || ty == 16));
+    if (!ok) return fail(LBM_EINVAL, "unsupported tile shape (tile_x, tile_y)");
+  }
   if (p->z_chunk < 0) return fail(LBM_EINVAL, "z_chunk must be >= 0");
   if (!(p->tau_nu > 0.5) || !(p->tau_kappa > 0.5)) return fail(LBM_EINVAL, "tau must be > 1/2");
   if (!(p->G <= 0.0) || !isfinite(p->G)) return fail(LBM_EINVAL, "G must be <= 0 and finite");
@@ -564,7 +576,7 @@ struct lbm_handle {
   double* prof;    // plane profiles (2 nz)
   int cur;
   int64_t t;
-  int tile_y, z_chunk;
+  int tile_x, tile_y, z_chunk;
 };
 
 namespace {
@@ -604,26 +616,42 @@ int grid_for(size_t n, int block) {
   return (int)g;
 }
 
-template <typename C, bool KEEP>
-int launch_fused(lbm_handle* h, const void* in, void* out) {
+template <typename C, int TX, int TY, bool KEEP>
+int launch_tile(lbm_handle* h, const void* in, void* out) {
   using R = typename C::R;
   const DevParams<R> P = dev_params<R>(h->p);
-  const int ty = h->tile_y;
-  const int ntx = (h->p.nx + 63) / 64, nty = (h->p.ny + ty - 1) / ty;
+  const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
   const int kz = h->z_chunk;
   const int nzc = (h->p.nz + kz - 1) / kz;
   const long long nblk = (long long)ntx * nty * nzc;
   if (nblk > 0x7fffffffLL) return fail(LBM_EINVAL, "grid too large");
-  const auto* i = (const typename C::S*)in;
-  auto* o = (typename C::S*)out;
-  switch (ty) {
-    case 1: hipLaunchKernelGGL((k_fused<C, 1, KEEP>), dim3(nblk), dim3(64), 0, h->stream, i, o, P, ntx, nty, kz); break;
-    case 2: hipLaunchKernelGGL((k_fused<C, 2, KEEP>), dim3(nblk), dim3(128), 0, h->stream, i, o, P, ntx, nty, kz); break;
-    case 4: hipLaunchKernelGGL((k_fused<C, 4, KEEP>), dim3(nblk), dim3(256), 0, h->stream, i, o, P, ntx, nty, kz); break;
-    default: hipLaunchKernelGGL((k_fused<C, 8, KEEP>), dim3(nblk), dim3(512), 0, h->stream, i, o, P, ntx, nty, kz); break;
-  }
+  hipLaunchKernelGGL((k_fused<C, TX, TY, KEEP>), dim3((unsigned)nblk), dim3(TX * TY), 0, h->stream,
+                     (const typename C::S*)in, (typename C::S*)out, P, ntx, nty, kz);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
+}
+
+// Tile shapes (TX x TY) the library is built for.  Keeping the next plane in
+// registers is only built for tiles of at most 512 threads.
+template <typename C, bool KEEP>
+int launch_fused(lbm_handle* h, const void* in, void* out) {
+  const int tx = h->tile_x, ty = h->tile_y;
+  if (tx == 64) {
+    switch (ty) {
+      case 1: return launch_tile<C, 64, 1, KEEP>(h, in, out);
+      case 2: return launch_tile<C, 64, 2, KEEP>(h, in, out);
+      case 4: return launch_tile<C, 64, 4, KEEP>(h, in, out);
+      case 8: return launch_tile<C, 64, 8, KEEP>(h, in, out);
+      case 16: return launch_tile<C, 64, 16, false>(h, in, out);
+    }
+  } else if (tx == 32) {
+    switch (ty) {
+      case 8: return launch_tile<C, 32, 8, KEEP>(h, in, out);
+      case 16: return launch_tile<C, 32, 16, KEEP>(h, in, out);
+      case 32: return launch_tile<C, 32, 32, false>(h, in, out);
+    }
+  }
+  return fail(LBM_EINVAL, "unsupported tile shape");
 }
 
 template <typename C>
@@ -679,7 +707,7 @@ template <typename C>
 int do_get(lbm_handle* h, double* st) {
   using R = typename C::R;
   const DevParams<R> P = dev_params<R>(h->p);
-  hipLaunchKernelGGL((k_get_state<C>), dim3(grid_for(2 * Q * h->L.N, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((k_get_state<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0,
                      h->stream, (const typename C::S*)h->buf[h->cur], st, P);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -689,7 +717,7 @@ template <typename C>
 int do_set(lbm_handle* h, const double* st) {
   using R = typename C::R;
   const DevParams<R> P = dev_params<R>(h->p);
-  hipLaunchKernelGGL((k_set_state<C>), dim3(grid_for(2 * Q * h->L.N, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((k_set_state<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0,
                      h->stream, (typename C::S*)h->buf[h->cur], st, P);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -818,8 +846,9 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->cur = 0;
   h->t = 0;
   // defaults from a tile/chunk sweep at 512^3 on MI355X
+  h->tile_x = p->tile_x ? p->tile_x : 64;
   h->tile_y = p->tile_y ? p->tile_y : (p->storage == LBM_FP64 ? 2 : 8);
-  h->z_chunk = p->z_chunk ? std::min(p->z_chunk, p->nz) : std::min(128, p->nz);
+  h->z_chunk = p->z_chunk ? std::min(p->z_chunk, p->nz) : std::min(512, p->nz);
   rc = dispatch<InitFn>(p->storage, h, rho0, T0);
   if (rc == LBM_OK) {
     hipError_t e = hipStreamSynchronize(h->stream);

@@ -65,33 +65,55 @@ struct F32 { using S = float; using R = float; };
 struct H16 { using S = uint16_t; using R = float; };
 struct B16 { using S = uint16_t; using R = float; };
 
+// Wave-uniform pointer: the value is moved into scalar registers so that a
+// load or store through it uses the scalar-base + 32-bit vector-offset form.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+// Element i of the population array starting at p; p MUST be the same for
+// every lane of the wave (it is read from the first active lane).  The byte
+// offset is formed in 32 bits (the library keeps every population array
+// below 4 GiB).
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* p, uint32_t i) {
+  return *(const T*)((const char*)uniform_ptr(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T& at32(T* p, uint32_t i) {
+  return *(T*)((char*)uniform_ptr(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 template <typename C> struct Codec;
-// p is a (wave-uniform) population base pointer, i a 32-bit node offset, so
-// that loads and stores use the scalar-base + 32-bit vector-offset form.
+// p is a population base pointer, i a 32-bit node offset.
 template <> struct Codec<F64> {
-  static __device__ __forceinline__ double ld(const double* p, uint32_t i, double) { return p[i]; }
-  static __device__ __forceinline__ void st(double* p, uint32_t i, double v, double) { p[i] = v; }
+  static __device__ __forceinline__ double ld(const double* p, uint32_t i, double) { return at32(p, i); }
+  static __device__ __forceinline__ void st(double* p, uint32_t i, double v, double) { at32(p, i) = v; }
 };
 template <> struct Codec<F32> {
-  static __device__ __forceinline__ float ld(const float* p, uint32_t i, float) { return p[i]; }
-  static __device__ __forceinline__ void st(float* p, uint32_t i, float v, float) { p[i] = v; }
+  static __device__ __forceinline__ float ld(const float* p, uint32_t i, float) { return at32(p, i); }
+  static __device__ __forceinline__ void st(float* p, uint32_t i, float v, float) { at32(p, i) = v; }
 };
 template <> struct Codec<H16> {
   static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
-    return (float)__builtin_bit_cast(_Float16, p[i]) + ref;
+    return (float)__builtin_bit_cast(_Float16, at32(p, i)) + ref;
   }
   static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
-    p[i] = __builtin_bit_cast(uint16_t, (_Float16)(v - ref));
+    at32(p, i) = __builtin_bit_cast(uint16_t, (_Float16)(v - ref));
   }
 };
 template <> struct Codec<B16> {
   static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
-    return __builtin_bit_cast(float, (uint32_t)p[i] << 16) + ref;
+    return __builtin_bit_cast(float, (uint32_t)at32(p, i) << 16) + ref;
   }
   static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
     uint32_t u = __builtin_bit_cast(uint32_t, v - ref);
     u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
-    p[i] = (uint16_t)(u >> 16);
+    at32(p, i) = (uint16_t)(u >> 16);
   }
 };
 

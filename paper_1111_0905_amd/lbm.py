@@ -32,7 +32,7 @@ class _CParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("periodic_z", ctypes.c_int32), ("kernel", ctypes.c_int32),
-        ("tile_y", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
+        ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
         ("tau_nu", ctypes.c_double), ("tau_kappa", ctypes.c_double), ("G", ctypes.c_double),
         ("T_d", ctypes.c_double), ("T_u", ctypes.c_double), ("gravity", ctypes.c_double),
         ("c_v", ctypes.c_double), ("rho_kappa", ctypes.c_double),
@@ -49,6 +49,7 @@ class Params:
     storage: int = LBM_FP32
     periodic_z: int = 0
     kernel: int = LBM_KERNEL_FUSED
+    tile_x: int = 0
     tile_y: int = 0
     z_chunk: int = 0
     tau_nu: float = 1.0

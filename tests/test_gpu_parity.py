@@ -108,16 +108,17 @@ def test_kernel_variants_agree_fp64(glbm):
     rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 11)
     kw = _kw(tau_nu=0.7, tau_kappa=0.9, gravity=1e-4)
     ref = None
-    for kernel, ty, zc in [(1, 0, 0), (0, 1, 0), (0, 2, 0), (0, 4, 0), (0, 8, 0), (0, 2, 5),
-                           (2, 4, 7), (2, 8, 0)]:
-        print(f"case: variant kernel={kernel} tile_y={ty} z_chunk={zc}", flush=True)
-        lat = _gpu(glbm, nx, ny, nz, rho0, 5, glbm.LBM_FP64, kernel=kernel, tile_y=ty,
-                   z_chunk=zc, **kw)
+    for kernel, tx, ty, zc in [(1, 0, 0, 0), (0, 64, 1, 0), (0, 64, 2, 0), (0, 64, 4, 0),
+                               (0, 64, 8, 0), (0, 64, 2, 5), (2, 64, 4, 7), (2, 64, 8, 0),
+                               (2, 64, 16, 3), (0, 32, 8, 0), (0, 32, 16, 9), (2, 32, 32, 0)]:
+        print(f"case: variant kernel={kernel} tile={tx}x{ty} z_chunk={zc}", flush=True)
+        lat = _gpu(glbm, nx, ny, nz, rho0, 5, glbm.LBM_FP64, kernel=kernel, tile_x=tx,
+                   tile_y=ty, z_chunk=zc, **kw)
         s = lat.state().cpu().numpy()
         if ref is None:
             ref = s
         else:
-            assert _rel(s, ref) < 1e-14, (kernel, ty, zc, _rel(s, ref))
+            assert _rel(s, ref) < 1e-14, (kernel, tx, ty, zc, _rel(s, ref))
 
 
 def fp32_tolerance():
