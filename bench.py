@@ -79,6 +79,30 @@ def run_storage(lbm, n, storage, steps, warmup, rho0, kernel=0, tile_y=0, z_chun
     return res, tot
 
 
+def source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1111_0905_amd", "csrc", "*.hip")) +
+                    glob.glob(os.path.join(ROOT, "paper_1111_0905_amd", "csrc", "*.hpp"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage, n):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on this very kernel source and workload (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_fused_{storage}_{n}cubed_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != source_hash():
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(seconds=15.0):
     """FP64 oracle on the host, 64^3 sample of the same physics."""
     import torch
@@ -195,7 +219,8 @@ def main():
                    "storage": args.storage, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(main_res["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(main_res["achieved_gbs"] / PEAK_HBM_GBS, 4), "traffic": None},
+                     "frac": round(main_res["achieved_gbs"] / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(args.storage, n)},
         "storage_forms": extra,
         "cpu_baseline": cpu,
     }
