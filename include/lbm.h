@@ -102,6 +102,7 @@ typedef struct lbm_params {
   int32_t tile_x;      /* fused-kernel tile width: 0 (default 64), 32 or 64 */
   int32_t tile_y;      /* fused-kernel tile height: 0 (default), 1..32, see lbm_init */
   int32_t z_chunk;     /* planes per fused-kernel work-group column (0 = default) */
+  int32_t adjoint;     /* 1 = reserve workspace for the lbm_adjoint_* entry points */
   double tau_nu, tau_kappa;
   double G;
   double T_d, T_u;
@@ -172,6 +173,41 @@ int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, dou
  * resets lbm_time to 0.  Both are asynchronous on the stream. */
 int lbm_get_state(lbm_handle* h, double* state);
 int lbm_set_state(lbm_handle* h, const double* state);
+
+/*
+ * Discrete adjoint (reverse mode) of one step, for gradients of objectives of
+ * the trajectory (SURVEY's differentiation form; the step is eqs. (LBEQ)/(LBEQ2)
+ * with everything of the Algorithm section, so its transposed Jacobian is
+ * exact up to rounding).  Needs a handle made with adjoint = 1; arithmetic in
+ * the handle's compute precision (FP64 for LBM_FP64, else FP32).
+ *   state:   device, canonical FP64 state s_t (the input of the step t -> t+1);
+ *   adj_in:  device, 38*N doubles, lambda_{t+1} = dJ/ds_{t+1};
+ *   adj_out: device, 38*N doubles, receives lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}
+ *            (must not alias adj_in);
+ *   grads:   host, 2 doubles, accumulated: [dJ/dG, dJ/dT_d] through this step
+ *            (T_d enters through the bottom-wall rule), may be NULL.
+ * Synchronises the stream.
+ */
+int lbm_adjoint_step(lbm_handle* h, const double* state, const double* adj_in, double* adj_out,
+                     double* grads);
+
+/*
+ * Wall heat flux q_bot = 2 kappa (T_d - Tbar(0)) of a canonical state (text
+ * before eq. (heat2); half-cell wall difference) and its adjoint:
+ *   q (host, may be NULL) receives q_bot;
+ *   adj (device, 38*N doubles, may be NULL) += weight * dq_bot/dstate;
+ *   grads (host, may be NULL): grads[1] += weight * dq_bot/dT_d = weight * 2 kappa.
+ * Needs walls.  Synchronises the stream.
+ */
+int lbm_adjoint_qbot(lbm_handle* h, const double* state, double weight, double* adj, double* q,
+                     double* grads);
+
+/*
+ * Gradient with respect to the initial density field of lbm_init, from
+ * lambda_0 (device, 38*N doubles) and the initial temperature T0 (device, N
+ * doubles, or NULL for the conduction profile): dJ_drho0 (device, N doubles).
+ */
+int lbm_adjoint_init_rho(lbm_handle* h, const double* adj0, const double* T0, double* dJ_drho0);
 
 /* Release the handle (the workspace stays the caller's). */
 void lbm_destroy(lbm_handle* h);

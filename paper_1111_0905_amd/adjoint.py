@@ -1,0 +1,111 @@
+"""Gradients of the wall-averaged heat flux through the hand-written adjoint.
+
+Objective (the differentiation form of the hot path):
+
+    J = (1/N_t) sum_{n=1}^{N_t} q_bot(s_n),   q_bot = 2 kappa (T_d - Tbar(0)),
+
+the conductive heat flux through the bottom wall (text before eq. (heat2);
+half-cell wall difference) averaged over the trajectory s_1..s_{N_t} of the
+step of eqs. (LBEQ)/(LBEQ2) from the local equilibrium of (rho0, T0).
+Gradients with respect to T_d (through the bottom-wall rule and q_bot; the
+initial T0 is held fixed), G (eq. (FORCE)) and the initial density field
+rho0.
+
+The forward pass keeps a canonical FP64 checkpoint every `ckpt_every`
+steps; the backward pass restores each checkpoint, recomputes its segment
+(storing the segment's states) and runs lbm_adjoint_step backwards through
+it.  All arithmetic runs in the HIP library; this module only sequences the
+calls and owns the device buffers.
+"""
+from __future__ import annotations
+
+from dataclasses import replace
+
+import numpy as np
+import torch
+
+from . import lbm
+
+
+def _kappa(p: lbm.Params) -> float:
+    return p.c_v * (p.tau_kappa - 0.5) * p.rho_kappa / 3.0
+
+
+def conduction_profile(p: lbm.Params, device="cuda") -> torch.Tensor:
+    """T0(k) = T_d + (T_u - T_d)(k + 1/2)/nz on every node (the lbm_init default)."""
+    k = torch.arange(p.nz, dtype=torch.float64, device=device)
+    Tz = p.T_d + (p.T_u - p.T_d) * (k + 0.5) / p.nz
+    return Tz.view(p.nz, 1, 1).expand(p.nz, p.ny, p.nx).contiguous().reshape(-1)
+
+
+def heat_flux_objective(p: lbm.Params, rho0, n_steps: int, T0=None):
+    """Forward only: J for the given parameters (used by finite differences)."""
+    T0 = conduction_profile(p) if T0 is None else T0
+    lat = lbm.Lattice(p, rho0, T0)
+    kappa, dT = _kappa(p), p.T_d - p.T_u
+    J = 0.0
+    for _ in range(n_steps):
+        lat.step(1)
+        nb, _, _, _ = lat.nusselt()
+        J += nb * kappa * dT / p.nz
+    return J / n_steps
+
+
+def heat_flux_gradients(p: lbm.Params, rho0, n_steps: int, ckpt_every: int = 20, T0=None):
+    """J and its gradients (dJ/drho0 [N], dJ/dT_d, dJ/dG) by checkpointed adjoint."""
+    p = replace(p, adjoint=1)
+    T0 = conduction_profile(p) if T0 is None else T0
+    rho0 = torch.as_tensor(rho0, dtype=torch.float64).cuda().contiguous().reshape(-1)
+    lat = lbm.Lattice(p, rho0, T0)
+    h = lat.h
+    ckpt = {0: lat.state().clone()}
+    J = 0.0
+    kappa, dT = _kappa(p), p.T_d - p.T_u
+    for n in range(1, n_steps + 1):
+        lat.step(1)
+        nb, _, _, _ = lat.nusselt()
+        J += nb * kappa * dT / p.nz
+        if n % ckpt_every == 0 and n < n_steps:
+            ckpt[n] = lat.state().clone()
+    J /= n_steps
+
+    grads = np.zeros(2)
+    lam = torch.zeros((38, p.nz, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    lam_new = torch.empty_like(lam)
+    starts = sorted(ckpt)
+    for si in range(len(starts) - 1, -1, -1):
+        b = starts[si]
+        e = starts[si + 1] if si + 1 < len(starts) else n_steps
+        lat.set_state(ckpt[b])
+        states = [ckpt[b]]
+        for _ in range(b + 1, e + 1):
+            lat.step(1)
+            states.append(lat.state().clone())
+        for t in range(e, b, -1):
+            lbm.lbm_adjoint_qbot(h, states[t - b], 1.0 / n_steps, lam, grads)
+            lbm.lbm_adjoint_step(h, states[t - 1 - b], lam, lam_new, grads)
+            lam, lam_new = lam_new, lam
+        del states
+    drho0 = lbm.lbm_adjoint_init_rho(h, lam, T0)
+    return J, drho0, float(grads[1]), float(grads[0])
+
+
+class HeatFluxObjective(torch.autograd.Function):
+    """torch.autograd.Function: (rho0, T_d, G) -> J with the hand-written adjoint.
+
+    forward(rho0 [N] float64 cuda, T_d (0-dim), G (0-dim), params, n_steps, ckpt_every)
+    """
+
+    @staticmethod
+    def forward(ctx, rho0, T_d, G, params, n_steps, ckpt_every):
+        p = replace(params, T_d=float(T_d), G=float(G))
+        T0 = conduction_profile(params)      # held fixed when T_d varies
+        J, drho0, dTd, dG = heat_flux_gradients(p, rho0, n_steps, ckpt_every, T0)
+        ctx.save_for_backward(drho0, torch.tensor(dTd, dtype=torch.float64),
+                              torch.tensor(dG, dtype=torch.float64))
+        return torch.tensor(J, dtype=torch.float64, device=rho0.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        drho0, dTd, dG = ctx.saved_tensors
+        return (gJ * drho0, gJ * dTd.to(gJ.device), gJ * dG.to(gJ.device), None, None, None)

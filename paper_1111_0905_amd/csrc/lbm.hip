@@ -500,6 +500,289 @@ __global__ void k_finish_nusselt(const double* __restrict__ prof, int nz, double
   }
 }
 
+// ---------------------------------------------------------------- adjoint
+//
+// Discrete adjoint of one step (the transpose of its Jacobian applied to
+// lambda_{t+1} = dJ/d state_{t+1}), in the handle's compute precision.  The
+// forward state is given in canonical FP64 form.  Three passes:
+//   k_adj_rhoE     rho and E of the forward state (for the stencils),
+//   k_adj_local    adjoint of streaming (gather) and of the node-local
+//                  collision, leaving the adjoints of the three stencil
+//                  gradients per node in scratch,
+//   k_adj_stencil  transpose of the gradient stencils (with the wall ghosts)
+//                  added to lambda_t.
+
+template <typename R>
+__global__ void k_adj_rhoE(const double* __restrict__ st, R* __restrict__ srho,
+                           R* __restrict__ sE, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    R r = R(0), e = R(0);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      r += (R)st[(size_t)l * N + n];
+      e += (R)st[(size_t)(l + Q) * N + n];
+    }
+    srho[n] = r;
+    sE[n] = e;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st,
+                                                   const double* __restrict__ lam1,
+                                                   double* __restrict__ lam0,
+                                                   const R* __restrict__ srho,
+                                                   const R* __restrict__ sE, R* __restrict__ gbar,
+                                                   DevParams<R> P, double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  double accG = 0.0, accTd = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    // forward quantities
+    R f[Q], g[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      f[l] = (R)st[(size_t)l * N + n];
+      g[l] = (R)st[(size_t)(l + Q) * N + n];
+    }
+    R rho, E;
+    moments<R>(f, g, rho, E);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    R gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz;
+    grad_w<R>([&](int l) { return nb.get(0, l); }, gpx, gpy, gpz);
+    grad_w<R>([&](int l) { return nb.get(2, l); }, gEx, gEy, gEz);
+    grad_w<R>([&](int l) { return nb.get(1, l); }, grx, gry, grz);
+    const R psi = psi_of<R>(rho);
+    const Macro<R> m = node_macro<R>(f, g, rho, E, psi, gpx, gpy, gpz, gEx, gEy, gEz, grx, gry,
+                                     grz, P);
+    const R ir = R(1) / rho;
+    const R ux = (m.jx + P.tau_nu * m.Fx) * ir;
+    const R uy = (m.jy + P.tau_nu * m.Fy) * ir;
+    const R uz = (m.jz + P.tau_nu * m.Fz) * ir;
+    const R uu = R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R vv = R(-1.5) * (m.vx * m.vx + m.vy * m.vy + m.vz * m.vz);
+
+    // adjoint of streaming: lambda of the collided populations
+    R as[Q], bs[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      int kk = k + CZ[l];
+      const int ii = wrap(i + CX[l], P.nx), jj = wrap(j + CY[l], P.ny);
+      if (kk >= 0 && kk < P.nz) {
+        const size_t o = ((size_t)kk * P.ny + jj) * P.nx + ii;
+        as[l] = (R)lam1[(size_t)l * N + o];
+        bs[l] = (R)lam1[(size_t)(l + Q) * N + o];
+      } else if (P.periodic_z) {
+        kk = kk < 0 ? kk + P.nz : kk - P.nz;
+        const size_t o = ((size_t)kk * P.ny + jj) * P.nx + ii;
+        as[l] = (R)lam1[(size_t)l * N + o];
+        bs[l] = (R)lam1[(size_t)(l + Q) * N + o];
+      } else {
+        const double lg = lam1[(size_t)(OPP[l] + Q) * N + n];
+        as[l] = (R)lam1[(size_t)OPP[l] * N + n];
+        bs[l] = (R)(-lg);
+        if (kk < 0) accTd += 2.0 * wlat<double>(l) * (double)P.rho_kappa * lg;
+      }
+    }
+
+    // adjoint of the BGK collisions
+    R rb = R(0), Eb = R(0), sbar = R(0);
+    R ubx = R(0), uby = R(0), ubz = R(0), vbx = R(0), vby = R(0), vbz = R(0);
+    const R gE = P.gamma * m.E;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const R w = wlat<R>(l);
+      const R cx = R(CX[l]), cy = R(CY[l]), cz = R(CZ[l]);
+      const R A = P.omega_f * as[l];
+      const R cu = cx * ux + cy * uy + cz * uz;
+      const R feq_over_rho = w * (uu + cu * (R(3) + R(4.5) * cu));
+      rb += A * feq_over_rho;
+      const R cf = A * w * rho;
+      const R tf = R(3) + R(9) * cu;
+      ubx += cf * (tf * cx - R(3) * ux);
+      uby += cf * (tf * cy - R(3) * uy);
+      ubz += cf * (tf * cz - R(3) * uz);
+      const R B = P.omega_g * bs[l];
+      sbar += w * bs[l];
+      const R cv = cx * m.vx + cy * m.vy + cz * m.vz;
+      Eb += B * (w * (R(1) + P.gamma * (vv + cv * (R(3) + R(4.5) * cv))) +
+                 bg<R>(l) * (P.rho_kappa * ir - R(1)));
+      rb += B * bg<R>(l) * (-P.rho_kappa * m.E * ir * ir);
+      const R cg = B * w * gE;
+      const R tg = R(3) + R(9) * cv;
+      vbx += cg * (tg * cx - R(3) * m.vx);
+      vby += cg * (tg * cy - R(3) * m.vy);
+      vbz += cg * (tg * cz - R(3) * m.vz);
+    }
+    // counter-term source S = (v . grad E) / c_v
+    vbx += sbar * gEx * P.inv_cv;
+    vby += sbar * gEy * P.inv_cv;
+    vbz += sbar * gEz * P.inv_cv;
+    R GEbx = sbar * m.vx * P.inv_cv, GEby = sbar * m.vy * P.inv_cv, GEbz = sbar * m.vz * P.inv_cv;
+    // u' = (j + tau F)/rho and v = (j + F/2)/rho
+    const R jbx = (ubx + vbx) * ir, jby = (uby + vby) * ir, jbz = (ubz + vbz) * ir;
+    const R Fbx = (P.tau_nu * ubx + R(0.5) * vbx) * ir;
+    const R Fby = (P.tau_nu * uby + R(0.5) * vby) * ir;
+    const R Fbz = (P.tau_nu * ubz + R(0.5) * vbz) * ir;
+    rb -= (ubx * ux + uby * uy + ubz * uz + vbx * m.vx + vby * m.vy + vbz * m.vz) * ir;
+    // F = -G psi grad psi - (grad E - grad rho / 3) - g rho z
+    const R Fdotgp = Fbx * gpx + Fby * gpy + Fbz * gpz;
+    const R psib = -P.G * Fdotgp;
+    accG += -(double)psi * (double)Fdotgp;
+    const R Gpbx = -P.G * psi * Fbx, Gpby = -P.G * psi * Fby, Gpbz = -P.G * psi * Fbz;
+    GEbx -= Fbx;
+    GEby -= Fby;
+    GEbz -= Fbz;
+    const R third = R(1) / R(3);
+    const R Grbx = third * Fbx, Grby = third * Fby, Grbz = third * Fbz;
+    rb -= P.gravity * Fbz;
+    rb += psib * psi * ir * ir;   // psi = exp(-1/rho)
+
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      lam0[(size_t)l * N + n] = (double)((R(1) - P.omega_f) * as[l] + rb +
+                                         (R(CX[l]) * jbx + R(CY[l]) * jby + R(CZ[l]) * jbz));
+      lam0[(size_t)(l + Q) * N + n] = (double)((R(1) - P.omega_g) * bs[l] + Eb);
+    }
+    gbar[n] = Gpbx;
+    gbar[N + n] = Gpby;
+    gbar[2 * N + n] = Gpbz;
+    gbar[3 * N + n] = GEbx;
+    gbar[4 * N + n] = GEby;
+    gbar[5 * N + n] = GEbz;
+    gbar[6 * N + n] = Grbx;
+    gbar[7 * N + n] = Grby;
+    gbar[8 * N + n] = Grbz;
+  }
+  const double sG = block_sum(accG, sh);
+  const double sT = block_sum(accTd, sh);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * 8] = sG;
+    partials[(size_t)blockIdx.x * 8 + 1] = sT;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R wdot(const R* gbar, size_t N, int comp, size_t o, int l) {
+  return R(CX[l]) * gbar[(size_t)(3 * comp) * N + o] + R(CY[l]) * gbar[(size_t)(3 * comp + 1) * N + o] +
+         R(CZ[l]) * gbar[(size_t)(3 * comp + 2) * N + o];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_stencil(const R* __restrict__ srho,
+                                                     const R* __restrict__ gbar,
+                                                     double* __restrict__ lam0, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    R pb = R(0), eb = R(0), qb = R(0);   // adjoints of psi, E, rho at this node
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      const R W = l < 7 ? R(1) / R(6) : R(1) / R(12);
+      const int ix = wrap(i - CX[l], P.nx), jx = wrap(j - CY[l], P.ny);
+      int kx = k - CZ[l];
+      bool real = kx >= 0 && kx < P.nz;
+      if (!real && P.periodic_z) {
+        kx = kx < 0 ? kx + P.nz : kx - P.nz;
+        real = true;
+      }
+      if (real) {  // node x = y - c_l reads this node in direction l
+        const size_t o = ((size_t)kx * P.ny + jx) * P.nx + ix;
+        pb += W * wdot(gbar, N, 0, o, l);
+        eb += W * wdot(gbar, N, 1, o, l);
+        qb += W * wdot(gbar, N, 2, o, l);
+      }
+      if (!P.periodic_z) {
+        // ghosts: a node x on a wall plane reading direction l across the
+        // wall sees psi of the wall-plane node (mirror) and 2 a(wall plane)
+        // - a(next plane) for E and rho (linear extrapolation)
+        const int kw = CZ[l] < 0 ? 0 : P.nz - 1;
+        const int ki = CZ[l] < 0 ? 1 : P.nz - 2;
+        if (CZ[l] != 0 && (k == kw || k == ki)) {
+          const size_t o = ((size_t)kw * P.ny + jx) * P.nx + ix;
+          if (k == kw) {
+            pb += W * wdot(gbar, N, 0, o, l);
+            eb += R(2) * W * wdot(gbar, N, 1, o, l);
+            qb += R(2) * W * wdot(gbar, N, 2, o, l);
+          }
+          if (k == ki) {
+            eb -= W * wdot(gbar, N, 1, o, l);
+            qb -= W * wdot(gbar, N, 2, o, l);
+          }
+        }
+      }
+    }
+    const R rho = srho[n];
+    const R psi = psi_of<R>(rho);
+    const double addf = (double)(qb + pb * psi / (rho * rho));
+    const double addg = (double)eb;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      lam0[(size_t)l * N + n] += addf;
+      lam0[(size_t)(l + Q) * N + n] += addg;
+    }
+  }
+}
+
+// lambda += weight * d q_bot / d state, q_bot = 2 kappa (T_d - mean_{k=0} E/rho);
+// out[blockIdx] partial of sum_{k=0} E/rho.
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_qbot(const double* __restrict__ st,
+                                                  double* __restrict__ lam, DevParams<R> P,
+                                                  double weight, double kappa,
+                                                  double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t A = (size_t)P.nx * P.ny;
+  double accT = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < A;
+       n += (size_t)gridDim.x * blockDim.x) {
+    double rho = 0.0, E = 0.0;
+    for (int l = 0; l < Q; ++l) {
+      rho += st[(size_t)l * N + n];
+      E += st[(size_t)(l + Q) * N + n];
+    }
+    accT += E / rho;
+    const double df = weight * 2.0 * kappa * E / (rho * rho * (double)A);
+    const double dg = -weight * 2.0 * kappa / (rho * (double)A);
+    if (lam) {
+      for (int l = 0; l < Q; ++l) {
+        lam[(size_t)l * N + n] += df;
+        lam[(size_t)(l + Q) * N + n] += dg;
+      }
+    }
+  }
+  const double s = block_sum(accT, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * 8] = s;
+}
+
+// dJ/drho0 from lambda_0: f = w rho0, g = w rho0 T0 + b (rho_kappa - rho0) T0.
+template <typename R>
+__global__ void k_adj_init(const double* __restrict__ lam, const double* __restrict__ T0,
+                           double* __restrict__ out, DevParams<R> P) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(n / ((size_t)P.nx * P.ny));
+    const double T = T0 ? T0[n]
+                        : (double)P.T_d + ((double)P.T_u - (double)P.T_d) * ((double)k + 0.5) / (double)P.nz;
+    double s = 0.0;
+    for (int l = 0; l < Q; ++l)
+      s += wlat<double>(l) * lam[(size_t)l * N + n] +
+           (wlat<double>(l) - bg<double>(l)) * T * lam[(size_t)(l + Q) * N + n];
+    out[n] = s;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 constexpr size_t kAlign = 256;
@@ -546,7 +829,7 @@ int validate(const lbm_params* p) {
 }
 
 struct Layout {
-  size_t N, pop_bytes, buf, scr, part, small, total;
+  size_t N, pop_bytes, buf, scr, part, small, adj, total;
 };
 
 Layout layout(const lbm_params* p) {
@@ -557,7 +840,8 @@ Layout layout(const lbm_params* p) {
   L.scr = align_up(L.N * real_bytes(p->storage));
   L.part = align_up((size_t)kDiagBlocks * 8 * sizeof(double));
   L.small = align_up((size_t)(16 + 4 * p->nz) * sizeof(double));
-  L.total = 2 * L.buf + 2 * L.scr + L.part + 2 * L.small;
+  L.adj = p->adjoint ? align_up((size_t)9 * L.N * real_bytes(p->storage)) : 0;
+  L.total = 2 * L.buf + 2 * L.scr + L.part + 2 * L.small + L.adj;
   return L;
 }
 
@@ -574,6 +858,7 @@ struct lbm_handle {
   double* partials;
   double* small;   // totals / nusselt results
   double* prof;    // plane profiles (2 nz)
+  void* gbar;      // adjoint scratch (9 N reals) or NULL
   int cur;
   int64_t t;
   int tile_x, tile_y, z_chunk;
@@ -777,6 +1062,62 @@ int do_nusselt(lbm_handle* h, double* nb, double* nt, double* nu_z, double* T_z)
   return LBM_OK;
 }
 
+template <typename R>
+int do_adjoint_step(lbm_handle* h, const double* st, const double* lam1, double* lam0,
+                    double* grads) {
+  const DevParams<R> P = dev_params<R>(h->p);
+  const size_t N = h->L.N;
+  hipLaunchKernelGGL((k_adj_rhoE<R>), dim3(grid_for(N, 256)), dim3(256), 0, h->stream, st,
+                     (R*)h->srho, (R*)h->sE, P);
+  HIP_TRY(hipGetLastError());
+  const int nblk = std::min(kDiagBlocks, grid_for(N, 256));
+  hipLaunchKernelGGL((k_adj_local<R>), dim3(nblk), dim3(256), 0, h->stream, st, lam1, lam0,
+                     (const R*)h->srho, (const R*)h->sE, (R*)h->gbar, P, h->partials);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_adj_stencil<R>), dim3(grid_for(N, 256)), dim3(256), 0, h->stream,
+                     (const R*)h->srho, (const R*)h->gbar, lam0, P);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
+  HIP_TRY(hipGetLastError());
+  double out[2];
+  HIP_TRY(hipMemcpyAsync(out, h->small, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (grads) {
+    grads[0] += out[0];
+    grads[1] += out[1];
+  }
+  return LBM_OK;
+}
+
+template <typename R>
+int do_adjoint_qbot(lbm_handle* h, const double* st, double weight, double* lam, double* q,
+                    double* grads) {
+  const DevParams<R> P = dev_params<R>(h->p);
+  const size_t A = (size_t)h->p.nx * h->p.ny;
+  const int nblk = std::min(kDiagBlocks, grid_for(A, 256));
+  const double kappa = h->p.c_v * (h->p.tau_kappa - 0.5) * h->p.rho_kappa / 3.0;
+  hipLaunchKernelGGL((k_adj_qbot<R>), dim3(nblk), dim3(256), 0, h->stream, st, lam, P, weight,
+                     kappa, h->partials);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
+  HIP_TRY(hipGetLastError());
+  double sumT;
+  HIP_TRY(hipMemcpyAsync(&sumT, h->small, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (q) *q = 2.0 * kappa * (h->p.T_d - sumT / (double)A);
+  if (grads) grads[1] += weight * 2.0 * kappa;
+  return LBM_OK;
+}
+
+template <typename R>
+int do_adjoint_init(lbm_handle* h, const double* lam0, const double* T0, double* out) {
+  const DevParams<R> P = dev_params<R>(h->p);
+  hipLaunchKernelGGL((k_adj_init<R>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
+                     lam0, T0, out, P);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
 template <template <typename> class Fn, typename... A>
 int dispatch(int storage, A... a) {
   switch (storage) {
@@ -842,7 +1183,8 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->sE = c; c += L.scr;
   h->partials = (double*)c; c += L.part;
   h->small = (double*)c; c += L.small;
-  h->prof = (double*)c;
+  h->prof = (double*)c; c += L.small;
+  h->gbar = L.adj ? (void*)c : nullptr;
   h->cur = 0;
   h->t = 0;
   // defaults from a tile/chunk sweep at 512^3 on MI355X
@@ -896,6 +1238,29 @@ int lbm_set_state(lbm_handle* h, const double* state) {
   const int rc = dispatch<SetFn>(h->p.storage, h, state);
   if (rc == LBM_OK) h->t = 0;
   return rc;
+}
+
+int lbm_adjoint_step(lbm_handle* h, const double* state, const double* adj_in, double* adj_out,
+                     double* grads) {
+  if (!h || !state || !adj_in || !adj_out) return fail(LBM_EINVAL, "NULL argument");
+  if (!h->gbar) return fail(LBM_EINVAL, "handle was created without adjoint = 1");
+  if (adj_in == adj_out) return fail(LBM_EINVAL, "adj_in and adj_out must not alias");
+  return h->p.storage == LBM_FP64 ? do_adjoint_step<double>(h, state, adj_in, adj_out, grads)
+                                  : do_adjoint_step<float>(h, state, adj_in, adj_out, grads);
+}
+
+int lbm_adjoint_qbot(lbm_handle* h, const double* state, double weight, double* adj, double* q,
+                     double* grads) {
+  if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
+  if (h->p.periodic_z) return fail(LBM_EINVAL, "the wall heat flux needs walls");
+  return h->p.storage == LBM_FP64 ? do_adjoint_qbot<double>(h, state, weight, adj, q, grads)
+                                  : do_adjoint_qbot<float>(h, state, weight, adj, q, grads);
+}
+
+int lbm_adjoint_init_rho(lbm_handle* h, const double* adj0, const double* T0, double* dJ_drho0) {
+  if (!h || !adj0 || !dJ_drho0) return fail(LBM_EINVAL, "NULL argument");
+  return h->p.storage == LBM_FP64 ? do_adjoint_init<double>(h, adj0, T0, dJ_drho0)
+                                  : do_adjoint_init<float>(h, adj0, T0, dJ_drho0);
 }
 
 void lbm_destroy(lbm_handle* h) { delete h; }

@@ -33,6 +33,7 @@ class _CParams(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("periodic_z", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
+        ("adjoint", ctypes.c_int32),
         ("tau_nu", ctypes.c_double), ("tau_kappa", ctypes.c_double), ("G", ctypes.c_double),
         ("T_d", ctypes.c_double), ("T_u", ctypes.c_double), ("gravity", ctypes.c_double),
         ("c_v", ctypes.c_double), ("rho_kappa", ctypes.c_double),
@@ -52,6 +53,7 @@ class Params:
     tile_x: int = 0
     tile_y: int = 0
     z_chunk: int = 0
+    adjoint: int = 0
     tau_nu: float = 1.0
     tau_kappa: float = 1.0
     G: float = -0.05 * math.e ** 2
@@ -93,6 +95,11 @@ def load_library(path: str = _LIB_PATH):
         "lbm_get_state": ([H, ctypes.c_void_p], ctypes.c_int),
         "lbm_set_state": ([H, ctypes.c_void_p], ctypes.c_int),
         "lbm_destroy": ([H], None),
+        "lbm_adjoint_step": ([H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, D], ctypes.c_int),
+        "lbm_adjoint_qbot": ([H, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, D, D],
+                             ctypes.c_int),
+        "lbm_adjoint_init_rho": ([H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                                 ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -193,6 +200,43 @@ def lbm_get_state(h: _Handle, out=None):
 def lbm_set_state(h: _Handle, state):
     import torch
     _check(load_library().lbm_set_state(h.h, _dev_ptr(state, torch.float64, 38 * h.p.n)))
+
+
+def lbm_adjoint_step(h: _Handle, state, adj_in, adj_out, grads=None):
+    """adj_out = (ds_{t+1}/ds_t)^T adj_in; grads (numpy float64[2]) += [dJ/dG, dJ/dT_d]."""
+    import torch
+    n = 38 * h.p.n
+    g = (ctypes.c_double * 2)(*(grads if grads is not None else [0.0, 0.0]))
+    _check(load_library().lbm_adjoint_step(h.h, _dev_ptr(state, torch.float64, n),
+                                           _dev_ptr(adj_in, torch.float64, n),
+                                           _dev_ptr(adj_out, torch.float64, n), g))
+    if grads is not None:
+        grads[0], grads[1] = g[0], g[1]
+    return adj_out
+
+
+def lbm_adjoint_qbot(h: _Handle, state, weight=0.0, adj=None, grads=None) -> float:
+    """q_bot of the state; adj += weight * dq/dstate; grads[1] += weight * dq/dT_d."""
+    import torch
+    n = 38 * h.p.n
+    q = ctypes.c_double()
+    g = (ctypes.c_double * 2)(*(grads if grads is not None else [0.0, 0.0]))
+    ap = _dev_ptr(adj, torch.float64, n) if adj is not None else None
+    _check(load_library().lbm_adjoint_qbot(h.h, _dev_ptr(state, torch.float64, n),
+                                           float(weight), ap, ctypes.byref(q), g))
+    if grads is not None:
+        grads[0], grads[1] = g[0], g[1]
+    return q.value
+
+
+def lbm_adjoint_init_rho(h: _Handle, adj0, T0=None, out=None):
+    import torch
+    if out is None:
+        out = torch.empty(h.p.n, dtype=torch.float64, device=adj0.device)
+    T0p = _dev_ptr(T0, torch.float64, h.p.n) if T0 is not None else None
+    _check(load_library().lbm_adjoint_init_rho(h.h, _dev_ptr(adj0, torch.float64, 38 * h.p.n),
+                                               T0p, _dev_ptr(out, torch.float64, h.p.n)))
+    return out
 
 
 def lbm_destroy(h: _Handle):
