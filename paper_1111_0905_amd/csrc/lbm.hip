@@ -237,7 +237,7 @@ __global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* _
 // ---------------------------------------------------------------- fused path
 
 // One work-group: tile of TX x TY nodes in x-y, planes [k0, k1) in z.
-// LDS ring buffer of three planes of psi, rho and E over the tile plus a
+// LDS ring buffer of four plane slots of psi, rho and E over the tile plus a
 // one-node ring; the populations of the plane being collided and of the next
 // plane are held in registers, so each population is read once from HBM.
 template <typename C, int TX, int TY, bool KEEP, typename R = typename C::R>
@@ -245,9 +245,12 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
                                                   typename C::S* __restrict__ out,
                                                   DevParams<R> P, int ntx, int nty, int kz) {
   constexpr int PW = TX + 2, PN = PW * (TY + 2);
-  __shared__ R sPsi[3][PN];
-  __shared__ R sRho[3][PN];
-  __shared__ R sE[3][PN];
+  // four plane slots: the plane written by fill(k+1) was last read by
+  // collide(k-2), so a single barrier per plane separates writers and readers
+  constexpr int NS = 4;
+  __shared__ R sPsi[NS][PN];
+  __shared__ R sRho[NS][PN];
+  __shared__ R sE[NS][PN];
 
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const size_t N = (size_t)nx * ny * nz;
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
     }
   };
 
-  auto slot = [&](int kp) { return ((kp - k0) % 3 + 3) % 3; };
+  auto slot = [&](int kp) { return (kp - k0 + NS) % NS; };
 
   // rho, E, psi of plane kp (global index, already wrapped) into LDS slot s;
   // the own populations are left in f, g when KEEP (else they are reloaded
@@ -369,7 +372,6 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       Streamer<C> em{out, P, N, i, j, k, im, ip, jm, jp};
       collide<R>(fa, ga, m, P, em);
     }
-    __syncthreads();
     if (KEEP) {
 #pragma unroll
       for (int l = 0; l < Q; ++l) {
