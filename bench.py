@@ -178,9 +178,9 @@ def main():
     rho0 = torch.from_numpy(synth.noisy_density(n, n, n, RHO_BOIL, 0.01, 1234)).cuda().reshape(-1)
 
     if args.sweep:
-        combos = [(0, 64, 8), (0, 64, 4), (0, 32, 8), (0, 64, 2), (2, 64, 8), (0, 32, 16)]
+        combos = [(0, 32, 16), (2, 64, 16), (0, 64, 8)]
         for kernel, tx, ty in combos:
-            for zc in (0,):
+            for zc in (0, 256, 128):
                 r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
                                    kernel, ty, zc, tx)
                 print(json.dumps({"kernel": kernel, "tile": [tx, ty], "z_chunk": zc,

@@ -64,7 +64,9 @@ enum {
 
 /* which implementation of the step */
 enum {
-  LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step, next plane kept in registers (default) */
+  LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step (default): with tile_x = tile_y = 0
+                                  the library picks the tile and whether the next plane stays in
+                                  registers from the storage type; with an explicit tile it does */
   LBM_KERNEL_REFERENCE = 1,    /* two plain kernels per step (moments, then collide+stream) */
   LBM_KERNEL_FUSED_RELOAD = 2  /* one z-marching kernel per step, populations re-read from cache */
 };

@@ -2,9 +2,9 @@
 // D3Q19 lattice Boltzmann step (arXiv:1111.0905, section "Algorithm").
 // The ABI is declared and documented in include/lbm.h.
 //
-// Data layout in HBM: structure of arrays, population q of node (i, j, k) at
-// q * N + (k * ny + j) * nx + i (i fastest), two ping-pong buffers holding
-// the post-streaming populations.  Streaming is a push: the collided value of
+// Data layout in HBM: structure of arrays of pairs: word l of node (i, j, k)
+// holds (f_l, g_l) at l * N + (k * ny + j) * nx + i (i fastest); two
+// ping-pong buffers hold the post-streaming populations.  Streaming is a push: the collided value of
 // node x in direction l is written to x + c_l of the other buffer; at the
 // walls it is written back to x in direction opp(l) (half-way bounce-back for
 // f, anti-bounce-back about w_l rho_kappa T_wall for g).
@@ -70,20 +70,17 @@ struct Streamer {
     const int jj = CY[l] > 0 ? jp : (CY[l] < 0 ? jm : j);
     if (kk >= 0 && kk < nz) {
       const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)l * N, o, fs, P.fref[l]);
-      Codec<C>::st(out + (size_t)(l + Q) * N, o, gs, P.gref[l]);
+      Codec<C>::st(out + (size_t)l * N, o, fs, gs, P.fref[l], P.gref[l]);
     } else if (P.periodic_z) {
       kk = kk < 0 ? kk + nz : kk - nz;
       const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)l * N, o, fs, P.fref[l]);
-      Codec<C>::st(out + (size_t)(l + Q) * N, o, gs, P.gref[l]);
+      Codec<C>::st(out + (size_t)l * N, o, fs, gs, P.fref[l], P.gref[l]);
     } else {  // the wall sends it back into this node in the opposite direction
       const R Tw = kk < 0 ? P.T_d : P.T_u;
       const int q = OPP[l];
       const uint32_t o = node_off(i, j, k, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)q * N, o, fs, P.fref[OPP[l]]);
-      Codec<C>::st(out + (size_t)(q + Q) * N, o, -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw,
-                   P.gref[OPP[l]]);
+      Codec<C>::st(out + (size_t)q * N, o, fs, -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw,
+                   P.fref[OPP[l]], P.gref[OPP[l]]);
     }
   }
 };
@@ -92,10 +89,7 @@ template <typename C, typename R = typename C::R>
 __device__ __forceinline__ void load_node(const typename C::S* __restrict__ in, size_t N, uint32_t o,
                                           const DevParams<R>& P, R* f, R* g) {
 #pragma unroll
-  for (int l = 0; l < Q; ++l) {
-    f[l] = Codec<C>::ld(in + (size_t)l * N, o, P.fref[l]);
-    g[l] = Codec<C>::ld(in + (size_t)(l + Q) * N, o, P.gref[l]);
-  }
+  for (int l = 0; l < Q; ++l) Codec<C>::ld(in + (size_t)l * N, o, f[l], g[l], P.fref[l], P.gref[l]);
 }
 
 // ---------------------------------------------------------------- init / state
@@ -116,10 +110,8 @@ __global__ void k_init(typename C::S* out, const double* __restrict__ rho0,
     R f[Q], g[Q];
     rest_equilibrium<R>((R)rho0[n], T, P, f, g);
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, f[l], P.fref[l]);
-      Codec<C>::st(out + (size_t)(l + Q) * N, (uint32_t)n, g[l], P.gref[l]);
-    }
+    for (int l = 0; l < Q; ++l)
+      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, f[l], g[l], P.fref[l], P.gref[l]);
   }
 }
 
@@ -145,11 +137,9 @@ __global__ void k_set_state(typename C::S* out, const double* __restrict__ st, D
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, (R)st[(size_t)l * N + n], P.fref[l]);
-      Codec<C>::st(out + (size_t)(l + Q) * N, (uint32_t)n, (R)st[(size_t)(l + Q) * N + n],
-                   P.gref[l]);
-    }
+    for (int l = 0; l < Q; ++l)
+      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, (R)st[(size_t)l * N + n],
+                   (R)st[(size_t)(l + Q) * N + n], P.fref[l], P.gref[l]);
   }
 }
 
@@ -299,16 +289,21 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
   // rho, E, psi of plane kp (global index, already wrapped) into LDS slot s;
   // the own populations are left in f, g when KEEP (else they are reloaded
   // from cache when the plane is collided).
-  auto fill = [&](int kp, int s, R* f, R* g) {
+  using S = typename C::S;
+  // the own node's stored words of plane kp go to w (KEEP) and are decoded
+  // again when the plane is collided; this keeps the 16-bit forms packed
+  auto fill = [&](int kp, int s, S* w) {
     if (active) {
-      R rho, E;
-      if (KEEP) {
-        load_node<C>(in, N, node_off(i, j, kp, nx, ny), P, f, g);
-        moments<R>(f, g, rho, E);
-      } else {
-        R ft[Q], gt[Q];
-        load_node<C>(in, N, node_off(i, j, kp, nx, ny), P, ft, gt);
-        moments<R>(ft, gt, rho, E);
+      const uint32_t o = node_off(i, j, kp, nx, ny);
+      R rho = R(0), E = R(0);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        const S v = at32(in + (size_t)l * N, o);
+        if (KEEP) w[l] = v;
+        R f, g;
+        Unpack<C>::run(v, f, g, P.fref[l], P.gref[l]);
+        rho += f;
+        E += g;
       }
       sRho[s][own_s] = rho;
       sE[s][own_s] = E;
@@ -336,20 +331,20 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
     }
   };
 
-  R fa[Q], ga[Q], fb[Q], gb[Q];
+  S wa[Q], wb[Q];
   const bool walls = !P.periodic_z;
   if (k0 > 0)
-    fill(k0 - 1, slot(k0 - 1), fb, gb);
+    fill(k0 - 1, slot(k0 - 1), wb);
   else if (!walls)
-    fill(nz - 1, slot(k0 - 1), fb, gb);
-  fill(k0, slot(k0), fa, ga);
+    fill(nz - 1, slot(k0 - 1), wb);
+  fill(k0, slot(k0), wa);
 
   for (int k = k0; k < k1; ++k) {
     const int kn = k + 1;
     if (kn < nz)
-      fill(kn, slot(kn), fb, gb);
+      fill(kn, slot(kn), wb);
     else if (!walls)
-      fill(0, slot(kn), fb, gb);
+      fill(0, slot(kn), wb);
     __syncthreads();
     if (walls && (k == 0 || kn == nz)) {
       if (k == 0) ghost(slot(-1), slot(0), slot(1));
@@ -357,7 +352,13 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       __syncthreads();
     }
     if (active) {
-      if (!KEEP) load_node<C>(in, N, node_off(i, j, k, nx, ny), P, fa, ga);
+      R fa[Q], ga[Q];
+      if (KEEP) {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) Unpack<C>::run(wa[l], fa[l], ga[l], P.fref[l], P.gref[l]);
+      } else {
+        load_node<C>(in, N, node_off(i, j, k, nx, ny), P, fa, ga);
+      }
       const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
       auto at = [&](const R(*A)[PN], int l) {
         const int s = CZ[l] < 0 ? sm : (CZ[l] > 0 ? sp : s0);
@@ -374,10 +375,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
     }
     if (KEEP) {
 #pragma unroll
-      for (int l = 0; l < Q; ++l) {
-        fa[l] = fb[l];
-        ga[l] = gb[l];
-      }
+      for (int l = 0; l < Q; ++l) wa[l] = wb[l];
     }
   }
 }
@@ -790,6 +788,7 @@ __global__ void k_adj_init(const double* __restrict__ lam, const double* __restr
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// bytes of one stored population (a stored word holds the pair f_l, g_l)
 size_t storage_bytes(int storage) {
   switch (storage) {
     case LBM_FP64: return 8;
@@ -805,8 +804,8 @@ int validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
   if (!p->periodic_z && p->nz < 2) return fail(LBM_EINVAL, "walls need nz >= 2");
-  if ((double)p->nx * p->ny * p->nz * (p->storage == LBM_FP64 ? 8.0 : 4.0) >= 4294967296.0)
-    return fail(LBM_EINVAL, "lattice too large (one population array must stay below 4 GiB)");
+  if ((double)p->nx * p->ny * p->nz * 2.0 * (double)storage_bytes(p->storage) >= 4294967296.0)
+    return fail(LBM_EINVAL, "lattice too large (one population-pair array must stay below 4 GiB)");
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16DEV) return fail(LBM_EINVAL, "unknown storage");
   if (p->kernel != LBM_KERNEL_FUSED && p->kernel != LBM_KERNEL_REFERENCE &&
       p->kernel != LBM_KERNEL_FUSED_RELOAD)
@@ -863,7 +862,7 @@ struct lbm_handle {
   void* gbar;      // adjoint scratch (9 N reals) or NULL
   int cur;
   int64_t t;
-  int tile_x, tile_y, z_chunk;
+  int kernel, tile_x, tile_y, z_chunk;
 };
 
 namespace {
@@ -969,7 +968,7 @@ int do_step(lbm_handle* h) {
   const void* in = h->buf[h->cur];
   void* out = h->buf[1 - h->cur];
   int rc;
-  switch (h->p.kernel) {
+  switch (h->kernel) {
     case LBM_KERNEL_FUSED: rc = launch_fused<C, true>(h, in, out); break;
     case LBM_KERNEL_FUSED_RELOAD: rc = launch_fused<C, false>(h, in, out); break;
     default: rc = launch_reference<C>(h, in, out); break;
@@ -1189,9 +1188,26 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->gbar = L.adj ? (void*)c : nullptr;
   h->cur = 0;
   h->t = 0;
-  // defaults from a tile/chunk sweep at 512^3 on MI355X
-  h->tile_x = p->tile_x ? p->tile_x : 64;
-  h->tile_y = p->tile_y ? p->tile_y : (p->storage == LBM_FP64 ? 2 : 8);
+  // defaults from tile/variant sweeps at 512^3 on MI355X: FP32 keeps the next
+  // plane in registers on 32 x 16 tiles; the 16-bit forms re-read it from
+  // cache on 64 x 16 tiles (four waves per SIMD)
+  h->kernel = p->kernel;
+  if (p->tile_x == 0 && p->tile_y == 0) {
+    if (p->storage == LBM_FP64) {
+      h->tile_x = 64;
+      h->tile_y = 2;
+    } else if (p->storage == LBM_FP32) {
+      h->tile_x = 32;
+      h->tile_y = 16;
+    } else {
+      h->tile_x = 64;
+      h->tile_y = 16;
+      if (p->kernel == LBM_KERNEL_FUSED) h->kernel = LBM_KERNEL_FUSED_RELOAD;
+    }
+  } else {
+    h->tile_x = p->tile_x ? p->tile_x : 64;
+    h->tile_y = p->tile_y ? p->tile_y : 8;
+  }
   h->z_chunk = p->z_chunk ? std::min(p->z_chunk, p->nz) : std::min(512, p->nz);
   rc = dispatch<InitFn>(p->storage, h, rho0, T0);
   if (rc == LBM_OK) {

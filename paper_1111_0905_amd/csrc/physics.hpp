@@ -58,12 +58,14 @@ struct DevParams {
 };
 
 // ----------------------------------------------------------- storage codecs
-// Populations are stored as S and computed in R.  The 16-bit forms store
-// (pop - pop_ref) and round to nearest even.
-struct F64 { using S = double; using R = double; };
-struct F32 { using S = float; using R = float; };
-struct H16 { using S = uint16_t; using R = float; };
-struct B16 { using S = uint16_t; using R = float; };
+// Populations are stored in pairs: word l of a node holds (f_l, g_l), so one
+// load or store moves both populations of a direction (push streaming sends
+// f*_l and g*_l to the same node, also at the walls).  Stored as S, computed
+// in R.  The 16-bit forms store (pop - pop_ref) and round to nearest even.
+struct F64 { using S = double2; using R = double; };
+struct F32 { using S = float2; using R = float; };
+struct H16 { using S = uint32_t; using R = float; };   // lo: f, hi: g (IEEE half)
+struct B16 { using S = uint32_t; using R = float; };   // lo: f, hi: g (bfloat16)
 
 // Wave-uniform pointer: the value is moved into scalar registers so that a
 // load or store through it uses the scalar-base + 32-bit vector-offset form.
@@ -89,31 +91,87 @@ __device__ __forceinline__ T& at32(T* p, uint32_t i) {
 }
 
 template <typename C> struct Codec;
-// p is a population base pointer, i a 32-bit node offset.
+// p is the (wave-uniform) base of direction l's pair array, i a 32-bit node
+// offset.
 template <> struct Codec<F64> {
-  static __device__ __forceinline__ double ld(const double* p, uint32_t i, double) { return at32(p, i); }
-  static __device__ __forceinline__ void st(double* p, uint32_t i, double v, double) { at32(p, i) = v; }
+  static __device__ __forceinline__ void ld(const double2* p, uint32_t i, double& f, double& g,
+                                            double, double) {
+    const double2 v = at32(p, i);
+    f = v.x;
+    g = v.y;
+  }
+  static __device__ __forceinline__ void st(double2* p, uint32_t i, double f, double g, double,
+                                            double) {
+    at32(p, i) = make_double2(f, g);
+  }
 };
 template <> struct Codec<F32> {
-  static __device__ __forceinline__ float ld(const float* p, uint32_t i, float) { return at32(p, i); }
-  static __device__ __forceinline__ void st(float* p, uint32_t i, float v, float) { at32(p, i) = v; }
+  static __device__ __forceinline__ void ld(const float2* p, uint32_t i, float& f, float& g, float,
+                                            float) {
+    const float2 v = at32(p, i);
+    f = v.x;
+    g = v.y;
+  }
+  static __device__ __forceinline__ void st(float2* p, uint32_t i, float f, float g, float, float) {
+    at32(p, i) = make_float2(f, g);
+  }
 };
 template <> struct Codec<H16> {
-  static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
-    return (float)__builtin_bit_cast(_Float16, at32(p, i)) + ref;
+  static __device__ __forceinline__ void ld(const uint32_t* p, uint32_t i, float& f, float& g,
+                                            float fr, float gr) {
+    const uint32_t u = at32(p, i);
+    f = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu)) + fr;
+    g = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16)) + gr;
   }
-  static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
-    at32(p, i) = __builtin_bit_cast(uint16_t, (_Float16)(v - ref));
+  static __device__ __forceinline__ void st(uint32_t* p, uint32_t i, float f, float g, float fr,
+                                            float gr) {
+    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)(f - fr));
+    const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)(g - gr));
+    at32(p, i) = lo | (hi << 16);
   }
 };
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+  return u >> 16;
+}
 template <> struct Codec<B16> {
-  static __device__ __forceinline__ float ld(const uint16_t* p, uint32_t i, float ref) {
-    return __builtin_bit_cast(float, (uint32_t)at32(p, i) << 16) + ref;
+  static __device__ __forceinline__ void ld(const uint32_t* p, uint32_t i, float& f, float& g,
+                                            float fr, float gr) {
+    const uint32_t u = at32(p, i);
+    f = __builtin_bit_cast(float, u << 16) + fr;
+    g = __builtin_bit_cast(float, u & 0xFFFF0000u) + gr;
   }
-  static __device__ __forceinline__ void st(uint16_t* p, uint32_t i, float v, float ref) {
-    uint32_t u = __builtin_bit_cast(uint32_t, v - ref);
-    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
-    at32(p, i) = (uint16_t)(u >> 16);
+  static __device__ __forceinline__ void st(uint32_t* p, uint32_t i, float f, float g, float fr,
+                                            float gr) {
+    at32(p, i) = bf16_rne(f - fr) | (bf16_rne(g - gr) << 16);
+  }
+};
+
+// Stored word -> (f, g) without touching memory (the word was loaded before).
+template <typename C> struct Unpack;
+template <> struct Unpack<F64> {
+  static __device__ __forceinline__ void run(double2 w, double& f, double& g, double, double) {
+    f = w.x;
+    g = w.y;
+  }
+};
+template <> struct Unpack<F32> {
+  static __device__ __forceinline__ void run(float2 w, float& f, float& g, float, float) {
+    f = w.x;
+    g = w.y;
+  }
+};
+template <> struct Unpack<H16> {
+  static __device__ __forceinline__ void run(uint32_t u, float& f, float& g, float fr, float gr) {
+    f = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu)) + fr;
+    g = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16)) + gr;
+  }
+};
+template <> struct Unpack<B16> {
+  static __device__ __forceinline__ void run(uint32_t u, float& f, float& g, float fr, float gr) {
+    f = __builtin_bit_cast(float, u << 16) + fr;
+    g = __builtin_bit_cast(float, u & 0xFFFF0000u) + gr;
   }
 };
 
