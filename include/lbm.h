@@ -89,6 +89,9 @@ enum {
  *   gravity >= 0: body force rho * (0, 0, -gravity).
  *   c_v > 0: specific heat at constant volume.
  *   rho_kappa > 0: density that sets the conductivity of g^eq.
+ *   T_lat: lattice temperature of f^eq (its second moment is rho T_lat delta
+ *     + rho u u); the rest of the ideal pressure, rho (T - T_lat), acts as a
+ *     force.  <= 0 picks the mean wall temperature.
  *   rho_ref, T_ref: reference state of the FP16/BF16 deviation storage
  *     (pop_ref = equilibrium at rest of (rho_ref, T_ref)); ignored otherwise.
  *   periodic_z: 0 = walls (nz >= 2), 1 = periodic in z as well.
@@ -112,6 +115,7 @@ typedef struct lbm_params {
   double c_v;
   double rho_kappa;
   double rho_ref, T_ref;
+  double T_lat;        /* lattice temperature of f^eq; <= 0 picks (T_d + T_u) / 2 */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

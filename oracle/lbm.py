@@ -27,9 +27,11 @@ rules.  The readings used here (each stated where it is used) are:
 * force weights W = 1/6 (axis) and 1/12 (face diagonal), i.e. sum W c c = 1;
   then the bulk non-ideal pressure is (G/2) exp(-2/rho), rho_c = 1,
   T_c = -G / e^2;
-* f^eq(u', rho) is the standard second-order polynomial equilibrium; the
-  dynamical temperature enters the f dynamics through the force
-  F_T = -grad(rho T - rho c_s^2), so that for G -> 0 the momentum equation
+* f^eq(u', rho) is the second-order polynomial equilibrium whose isotropic
+  second moment is rho T_lat (a constant lattice temperature, by default the
+  mean wall temperature, set through the rest population); the dynamical
+  temperature enters the f dynamics through the force
+  F_T = -grad(rho T - rho T_lat), so that for G -> 0 the momentum equation
   sees the second moment rho T delta + rho u u (the f/g coupling);
 * g^eq(u, F, T): polynomial equilibrium of E = rho T whose first moment is
   gamma E v (gamma = 1 + 1/c_v; v = (j + F/2)/rho carries the force) and
@@ -49,10 +51,13 @@ rules.  The readings used here (each stated where it is used) are:
   extrapolated linearly through the wall (a conductive state at rest is then
   an exact steady state with Nu = 1).
 
-A literal reading that puts T into the rest population of f^eq and adds the
-counter-term as -(E/c_v) div v is linearly unstable at the paper's
-viscosity; the readings above are linearly stable there for critical
-temperatures T_c <~ 0.05 (the default; see the stability test).
+A literal reading that puts the dynamical T into the rest population of
+f^eq and adds the counter-term as -(E/c_v) div v is linearly unstable at the
+paper's viscosity; the readings above are linearly stable there for critical
+temperatures T_c <~ 0.05 (the default; see the stability test).  With the
+constant T_lat in f^eq only the small part rho (T - T_lat) of the ideal
+pressure goes through the stencil force, which keeps the coexistence
+densities on the Maxwell construction (Fig. 1).
 
 Populations are stored as tensors of shape (19, nz, ny, nx), fields as
 (nz, ny, nx), vectors as (3, nz, ny, nx); all float64 on the CPU.  Every
@@ -85,7 +90,8 @@ OPP = [0] + [l + 1 if l % 2 == 1 else l - 1 for l in range(1, 19)]
 W_LAT = torch.tensor([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12, dtype=DT)
 # pseudopotential-force weights, isotropic to 4th order, sum W c c = identity
 W_FOR = torch.tensor([0.0] + [1.0 / 6.0] * 6 + [1.0 / 12.0] * 12, dtype=DT)
-# isotropic second-moment adjuster of g^eq
+# isotropic second-moment adjusters of f^eq (a) and g^eq (b)
+A_F = torch.tensor([-2.0] + [3.0 / 18.0] * 6 + [3.0 / 36.0] * 12, dtype=DT)
 B_G = torch.tensor([-2.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12, dtype=DT)
 CS2 = 1.0 / 3.0
 
@@ -105,6 +111,7 @@ class Params:
     c_v: float = 1.0
     rho_kappa: float = 0.5
     periodic_z: bool = False
+    T_lat: float = 0.0          # lattice temperature of f^eq; 0 -> (T_d + T_u) / 2
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)
@@ -122,6 +129,10 @@ class Params:
     @property
     def T_c(self) -> float:
         return -self.G / math.e ** 2
+
+    @property
+    def T_lattice(self) -> float:
+        return self.T_lat if self.T_lat > 0 else 0.5 * (self.T_d + self.T_u)
 
 
 # ---------------------------------------------------------------- stencils
@@ -200,27 +211,29 @@ def forces(p: Params, rho, E, G=None):
     """Total force on the f populations and the two gradients the g update
     needs.
 
-    F = F_SC + F_T + rho (0, 0, -g), where F_T = -grad[rho T - rho c_s^2]
-    brings the ideal pressure rho T (T taken from the g populations) into
-    the momentum equation in place of the lattice's own rho c_s^2: in the
-    limit G -> 0 the f dynamics then carries the second moment
-    rho T delta + rho u u.  The gradients of E and rho use ghost planes
-    extrapolated linearly through the walls (psi uses the mirror image).
+    F = F_SC + F_T + rho (0, 0, -g), where F_T = -grad[rho T - rho T_lat]
+    adds to the lattice pressure rho T_lat of f^eq the rest of the ideal
+    pressure rho T (T taken from the g populations): in the limit G -> 0 the
+    f dynamics then carries the second moment rho T delta + rho u u.  The
+    gradients of E and rho use ghost planes extrapolated linearly through the
+    walls (psi uses the mirror image).
     """
     gE = _grad_w(p, E, "linear")
     grho = _grad_w(p, rho, "linear")
-    F = sc_force(p, rho, G) - (gE - CS2 * grho)
+    F = sc_force(p, rho, G) - (gE - p.T_lattice * grho)
     F = F + torch.stack([torch.zeros_like(rho), torch.zeros_like(rho), -p.gravity * rho])
     return F, gE, grho
 
 
-def f_equilibrium(rho, u) -> torch.Tensor:
-    """f^eq_l(u', rho): second-order polynomial (Hermite) equilibrium of the
-    D3Q19 lattice, moments rho, rho u, rho c_s^2 delta + rho u u."""
+def f_equilibrium(rho, u, T_lat=CS2) -> torch.Tensor:
+    """f^eq_l(u', rho): second-order polynomial equilibrium of the D3Q19
+    lattice with moments rho, rho u, rho T_lat delta + rho u u (the rest
+    population carries rho (T_lat - c_s^2) a_l, a_0 = -2, a_l = 3 w_l)."""
     cu = torch.einsum("la,azyx->lzyx", C, u)
     uu = (u * u).sum(0)
     w = W_LAT.view(Q19, 1, 1, 1)
-    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
+    a = A_F.view(Q19, 1, 1, 1)
+    return w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) + a * rho * (T_lat - CS2)
 
 
 def g_equilibrium(p: Params, rho, E, v, T, v_lin=None) -> torch.Tensor:
@@ -266,7 +279,7 @@ def macroscopic(p: Params, f: torch.Tensor, g: torch.Tensor, G=None) -> dict:
 def collide(p: Params, f, g, G=None):
     """Right-hand sides of eqs. (LBEQ)/(LBEQ2) plus the counter-term source."""
     m = macroscopic(p, f, g, G)
-    feq = f_equilibrium(m["rho"], m["u_shift"])
+    feq = f_equilibrium(m["rho"], m["u_shift"], p.T_lattice)
     geq = g_equilibrium(p, m["rho"], m["E"], m["v"], m["T"])
     fs = f - (f - feq) / p.tau_nu
     gs = g - (g - geq) / p.tau_kappa + W_LAT.view(Q19, 1, 1, 1) * m["S"]
@@ -328,7 +341,7 @@ def init_state(p: Params, rho0, T0=None):
     rho0 = torch.as_tensor(rho0, dtype=DT)
     T0 = initial_temperature(p) if T0 is None else torch.as_tensor(T0, dtype=DT)
     zero = torch.zeros((3,) + tuple(rho0.shape), dtype=DT)
-    f = f_equilibrium(rho0, zero)
+    f = f_equilibrium(rho0, zero, p.T_lattice)
     g = g_equilibrium(p, rho0, rho0 * T0, zero, T0)
     return f, g
 

@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st
       const R cx = R(CX[l]), cy = R(CY[l]), cz = R(CZ[l]);
       const R A = P.omega_f * as[l];
       const R cu = cx * ux + cy * uy + cz * uz;
-      const R feq_over_rho = w * (uu + cu * (R(3) + R(4.5) * cu));
+      const R feq_over_rho = w * (uu + cu * (R(3) + R(4.5) * cu)) + af<R>(l) * (P.T_lat - R(1) / R(3));
       rb += A * feq_over_rho;
       const R cf = A * w * rho;
       const R tf = R(3) + R(9) * cu;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st
     const R Fby = (P.tau_nu * uby + R(0.5) * vby) * ir;
     const R Fbz = (P.tau_nu * ubz + R(0.5) * vbz) * ir;
     rb -= (ubx * ux + uby * uy + ubz * uz + vbx * m.vx + vby * m.vy + vbz * m.vz) * ir;
-    // F = -G psi grad psi - (grad E - grad rho / 3) - g rho z
+    // F = -G psi grad psi - (grad E - T_lat grad rho) - g rho z
     const R Fdotgp = Fbx * gpx + Fby * gpy + Fbz * gpz;
     const R psib = -P.G * Fdotgp;
     accG += -(double)psi * (double)Fdotgp;
@@ -639,8 +639,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st
     GEbx -= Fbx;
     GEby -= Fby;
     GEbz -= Fbz;
-    const R third = R(1) / R(3);
-    const R Grbx = third * Fbx, Grby = third * Fby, Grbz = third * Fbz;
+    const R Grbx = P.T_lat * Fbx, Grby = P.T_lat * Fby, Grbz = P.T_lat * Fbz;
     rb -= P.gravity * Fbz;
     rb += psib * psi * ir * ir;   // psi = exp(-1/rho)
 
@@ -765,7 +764,8 @@ __global__ __launch_bounds__(256) void k_adj_qbot(const double* __restrict__ st,
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * 8] = s;
 }
 
-// dJ/drho0 from lambda_0: f = w rho0, g = w rho0 T0 + b (rho_kappa - rho0) T0.
+// dJ/drho0 from lambda_0: f = w rho0 + a rho0 (T_lat - 1/3),
+// g = w rho0 T0 + b (rho_kappa - rho0) T0.
 template <typename R>
 __global__ void k_adj_init(const double* __restrict__ lam, const double* __restrict__ T0,
                            double* __restrict__ out, DevParams<R> P) {
@@ -777,7 +777,7 @@ __global__ void k_adj_init(const double* __restrict__ lam, const double* __restr
                         : (double)P.T_d + ((double)P.T_u - (double)P.T_d) * ((double)k + 0.5) / (double)P.nz;
     double s = 0.0;
     for (int l = 0; l < Q; ++l)
-      s += wlat<double>(l) * lam[(size_t)l * N + n] +
+      s += (wlat<double>(l) + af<double>(l) * ((double)P.T_lat - 1.0 / 3.0)) * lam[(size_t)l * N + n] +
            (wlat<double>(l) - bg<double>(l)) * T * lam[(size_t)(l + Q) * N + n];
     out[n] = s;
   }
@@ -884,12 +884,14 @@ DevParams<R> dev_params(const lbm_params& p) {
   d.rho_kappa = (R)p.rho_kappa;
   d.T_d = (R)p.T_d;
   d.T_u = (R)p.T_u;
+  const double T_lat = p.T_lat > 0.0 ? p.T_lat : 0.5 * (p.T_d + p.T_u);
+  d.T_lat = (R)T_lat;
   const bool dev = p.storage >= LBM_FP16DEV;
   for (int l = 0; l < Q; ++l) {
     // reference populations: equilibrium at rest of (rho_ref, T_ref)
     const double E = p.rho_ref * p.T_ref;
     const double w = wlat<double>(l);
-    d.fref[l] = dev ? (R)(w * p.rho_ref) : R(0);
+    d.fref[l] = dev ? (R)(w * p.rho_ref + af<double>(l) * p.rho_ref * (T_lat - 1.0 / 3.0)) : R(0);
     d.gref[l] = dev ? (R)(w * E + bg<double>(l) * (p.rho_kappa - p.rho_ref) * p.T_ref) : R(0);
   }
   return d;

@@ -6,12 +6,15 @@
 //   eq. (HYDRO)  rho = sum f, j = sum c f, E = rho T = sum g;
 //   eq. (FORCE)  F_SC = -G psi(x) sum_l W_l c_l psi(x + c_l), psi = exp(-1/rho),
 //                W = 1/6 (axis), 1/12 (face diagonal): isotropic to 4th order;
-//   f/g coupling: F_T = -grad(rho T - rho/3) puts the ideal pressure rho T
-//                 (T from the g populations) into the momentum equation;
+//   f/g coupling: f^eq carries the lattice pressure rho T_lat (constant
+//                 lattice temperature, via the rest population) and the force
+//                 F_T = -grad(rho T - rho T_lat) adds the rest of the ideal
+//                 pressure rho T (T from the g populations);
 //   gravity:      F_g = rho (0, 0, -g)  (eq. (ns));
 //   velocity shift u' = (j + tau_nu F)/rho inside f^eq; physical v = (j + F/2)/rho;
 //   eqs. (LBEQ)/(LBEQ2) BGK with
-//     f^eq_l = w_l rho [1 + 3 c.u' + 4.5 (c.u')^2 - 1.5 u'^2],
+//     f^eq_l = w_l rho [1 + 3 c.u' + 4.5 (c.u')^2 - 1.5 u'^2] + a_l rho (T_lat - 1/3),
+//       a_0 = -2, a_l = 3 w_l,
 //     g^eq_l = w_l [E + gamma E (3 c.v + 4.5 (c.v)^2 - 1.5 v^2)] + b_l (rho_kappa - rho) T,
 //       gamma = 1 + 1/c_v, b_0 = -2/3, b_l = w_l: one conductivity
 //       kappa = c_v (tau_kappa - 1/2) rho_kappa / 3 in both phases;
@@ -36,7 +39,11 @@ template <typename R>
 __host__ __device__ constexpr R wlat(int l) {
   return l == 0 ? R(1) / R(3) : (l < 7 ? R(1) / R(18) : R(1) / R(36));
 }
-// isotropic second-moment adjuster of g^eq
+// isotropic second-moment adjusters of f^eq (a) and g^eq (b)
+template <typename R>
+__host__ __device__ constexpr R af(int l) {
+  return l == 0 ? R(-2) : R(3) * wlat<R>(l);
+}
 template <typename R>
 __host__ __device__ constexpr R bg(int l) {
   return l == 0 ? R(-2) / R(3) : wlat<R>(l);
@@ -54,6 +61,7 @@ struct DevParams {
   R inv_cv, gamma;      // 1/c_v, 1 + 1/c_v
   R rho_kappa;
   R T_d, T_u;
+  R T_lat;              // lattice temperature of f^eq
   R fref[Q], gref[Q];   // deviation references (16-bit storage only)
 };
 
@@ -225,11 +233,10 @@ __device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R 
   m.jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
   m.jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
   m.jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
-  const R third = R(1) / R(3);
   const R gp = -P.G * psi;
-  m.Fx = gp * gpx - (gEx - third * grx);
-  m.Fy = gp * gpy - (gEy - third * gry);
-  m.Fz = gp * gpz - (gEz - third * grz) - P.gravity * rho;
+  m.Fx = gp * gpx - (gEx - P.T_lat * grx);
+  m.Fy = gp * gpy - (gEy - P.T_lat * gry);
+  m.Fz = gp * gpz - (gEz - P.T_lat * grz) - P.gravity * rho;
   const R ir = R(1) / rho;
   m.vx = (m.jx + R(0.5) * m.Fx) * ir;
   m.vy = (m.jy + R(0.5) * m.Fy) * ir;
@@ -252,12 +259,13 @@ __device__ __forceinline__ void collide(const R* f, const R* g, const Macro<R>& 
   const R vv = R(-1.5) * (m.vx * m.vx + m.vy * m.vy + m.vz * m.vz);
   const R gE = P.gamma * m.E;
   const R rk = (P.rho_kappa - m.rho) * m.T;
+  const R rt = m.rho * (P.T_lat - R(1) / R(3));
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
     const R cu = R(CX[l]) * ux + R(CY[l]) * uy + R(CZ[l]) * uz;
     const R cv = R(CX[l]) * m.vx + R(CY[l]) * m.vy + R(CZ[l]) * m.vz;
     const R w = wlat<R>(l);
-    const R feq = w * m.rho * (uu + cu * (R(3) + R(4.5) * cu));
+    const R feq = w * m.rho * (uu + cu * (R(3) + R(4.5) * cu)) + af<R>(l) * rt;
     const R geq = w * (m.E + gE * (vv + cv * (R(3) + R(4.5) * cv))) + bg<R>(l) * rk;
     const R fs = f[l] - P.omega_f * (f[l] - feq);
     const R gs = g[l] - P.omega_g * (g[l] - geq) + w * m.S;
@@ -270,9 +278,10 @@ template <typename R>
 __device__ __forceinline__ void rest_equilibrium(R rho, R T, const DevParams<R>& P, R* f, R* g) {
   const R E = rho * T;
   const R rk = (P.rho_kappa - rho) * T;
+  const R rt = rho * (P.T_lat - R(1) / R(3));
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
-    f[l] = wlat<R>(l) * rho;
+    f[l] = wlat<R>(l) * rho + af<R>(l) * rt;
     g[l] = wlat<R>(l) * E + bg<R>(l) * rk;
   }
 }

@@ -37,7 +37,7 @@ class _CParams(ctypes.Structure):
         ("tau_nu", ctypes.c_double), ("tau_kappa", ctypes.c_double), ("G", ctypes.c_double),
         ("T_d", ctypes.c_double), ("T_u", ctypes.c_double), ("gravity", ctypes.c_double),
         ("c_v", ctypes.c_double), ("rho_kappa", ctypes.c_double),
-        ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("T_lat", ctypes.c_double),
     ]
 
 
@@ -64,6 +64,7 @@ class Params:
     rho_kappa: float = 0.5
     rho_ref: float = 1.0
     T_ref: float = 0.045
+    T_lat: float = 0.0
 
     def c(self) -> _CParams:
         return _CParams(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -6,13 +6,13 @@ retyping of the oracle's own formula:
   fourth-order isotropy (textbook D3Q19);
 * force weights: eq. (FORCE) asks for isotropy up to 4th order; with the
   normalisation sum W c c = 1 the bulk pressure becomes (G/2) exp(-2/rho);
-* f^eq moments: rho, rho u', rho c_s^2 delta + rho u'u' (polynomial
-  equilibrium of the lattice, Algorithm section);
+* f^eq moments: rho, rho u', rho T_lat delta + rho u'u' (polynomial
+  equilibrium of the lattice with the lattice temperature T_lat);
 * g^eq moments: rho T, gamma rho T v_g, and an isotropic second moment
   independent of the local density (one conductivity in both phases,
   Table 1);
 * the thermal force reproduces the ideal pressure gradient: for G = 0 the
-  net force F + lattice pressure gradient equals -grad(rho T).
+  net force F - grad(rho T_lat) (lattice pressure) equals -grad(rho T).
 """
 import itertools
 
@@ -77,15 +77,16 @@ def _random_fields(n=5, seed=0):
     return rho, u, T
 
 
-def test_f_equilibrium_moments():
+@pytest.mark.parametrize("T_lat", [1.0 / 3.0, 0.045])
+def test_f_equilibrium_moments(T_lat):
     rho, u, T = _random_fields()
-    feq = lbm.f_equilibrium(rho, u)
+    feq = lbm.f_equilibrium(rho, u, T_lat)
     assert torch.allclose(feq.sum(0), rho, rtol=0, atol=1e-14)
     j = torch.einsum("la,lzyx->azyx", C, feq)
     assert torch.allclose(j, rho * u, rtol=0, atol=1e-14)
     for a, b in itertools.product(range(3), repeat=2):
         m2 = (C[:, a].view(19, 1, 1, 1) * C[:, b].view(19, 1, 1, 1) * feq).sum(0)
-        want = rho * u[a] * u[b] + (rho / 3.0 if a == b else 0.0)
+        want = rho * u[a] * u[b] + (rho * T_lat if a == b else 0.0)
         assert torch.allclose(m2, want, rtol=0, atol=1e-14)
 
 
@@ -106,7 +107,7 @@ def test_g_equilibrium_moments():
 
 
 def test_thermal_force_gives_ideal_pressure_gradient():
-    """G = 0, no gravity: F + (lattice pressure gradient rho c_s^2) is the
+    """G = 0, no gravity: F - (lattice pressure gradient of rho T_lat) is the
     W-stencil gradient of -rho T, i.e. the fluid feels P0 = rho T."""
     n = 64
     p = lbm.Params(1, 1, n, G=0.0, periodic_z=True)
@@ -117,7 +118,7 @@ def test_thermal_force_gives_ideal_pressure_gradient():
     F, gE, grho = lbm.forces(p, rho, rho * T)
     P0 = (rho * T).view(n)
     dP = (torch.roll(P0, -1) - torch.roll(P0, 1)) / 2   # central difference
-    got = F[2].view(n) - grho[2].view(n) / 3.0
+    got = F[2].view(n) - p.T_lattice * grho[2].view(n)   # force minus lattice pressure gradient
     assert torch.allclose(got, -dP, rtol=0, atol=1e-15)
 
 

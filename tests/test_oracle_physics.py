@@ -30,7 +30,7 @@ T0 = 0.05   # working temperature of the tests (the default critical temperature
 
 
 def _state(p, rho, u, T):
-    f = lbm.f_equilibrium(rho, u)
+    f = lbm.f_equilibrium(rho, u, p.T_lattice)
     g = lbm.g_equilibrium(p, rho, rho * T, u, T)
     return f, g
 
