@@ -1,0 +1,288 @@
+"""Drivers for the measured workloads of the boiling convection cell.
+
+  python -m paper_1111_0905_amd.experiments convection --n 128 --rho 1.93 --ra 1e6 --steps 20000
+  python -m paper_1111_0905_amd.experiments pair --n 512 --steps 50000      (boiling vs single phase)
+  python -m paper_1111_0905_amd.experiments precision --n 512 --steps 5000  (FP32 vs FP16/BF16 storage)
+  python -m paper_1111_0905_amd.experiments adjoint --n 64 --steps 400      (checkpointed gradients)
+
+Every lattice update and every diagnostic reduction runs in the HIP library;
+this module only sequences calls and post-processes the returned profiles
+(time series, plane averages) and, for the bubble statistics, the density
+field copied to the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import lbm, thermo
+
+TC = 0.12                          # linear stability margin at tau_nu = 0.5495 ends near 0.16
+NU = 0.0165                       # kinematic viscosity of Table 1
+
+
+def cell_params(n, rho_mean, Ra, storage="fp32", T_c=TC, tau_nu=0.5 + 3 * NU, Pr=9.0,
+                rho_kappa=0.5, c_v=1.0, periodic_z=0, **kw):
+    """Parameters of the convection cell: T_d = 0.95 T_c, T_u = 0.85 T_c,
+    tau_kappa from Pr = 9 in the liquid at the mid temperature (Table 1),
+    gravity from the Rayleigh number at mid height."""
+    G = thermo.coupling_for_tc(T_c)
+    T_d, T_u = 0.95 * T_c, 0.85 * T_c
+    Tm = 0.5 * (T_d + T_u)
+    tau_kappa = thermo.tau_kappa_for_prandtl(Pr, (tau_nu - 0.5) / 3.0, rho_mean, Tm, G,
+                                             rho_kappa, c_v)
+    if Ra > 0:
+        ra_max = thermo.max_rayleigh(n, rho_mean, T_d, T_u, G, tau_nu, tau_kappa, rho_kappa, c_v)
+        Ra_eff = min(Ra, 0.7 * ra_max)   # beyond this the adiabatic gradient takes over
+        g = thermo.gravity_for_rayleigh(Ra_eff, n, rho_mean, T_d, T_u, G, tau_nu, tau_kappa,
+                                        rho_kappa, c_v)
+    else:
+        Ra_eff, g = 0.0, 0.0
+    p = lbm.Params(n, n, n, storage=lbm.STORAGE[storage], tau_nu=tau_nu, tau_kappa=tau_kappa,
+                   G=G, T_d=T_d, T_u=T_u, gravity=g, c_v=c_v, rho_kappa=rho_kappa,
+                   rho_ref=rho_mean, T_ref=Tm, periodic_z=periodic_z, **kw)
+    p.rayleigh = Ra_eff
+    return p
+
+
+BOIL_MARGIN = 0.045
+
+
+def boiling_density(n, Ra, T_c=TC, margin=BOIL_MARGIN, **kw):
+    """Mean density of the boiling cell: `margin` below the mean density of
+    the hydrostatic liquid column whose bottom layer sits on the liquid
+    spinodal (the margin equals the zero-gravity gap between 1.93 and the
+    1.975 threshold).  Gravity depends on the density through Ra, so the
+    two are iterated to a fixed point."""
+    G = thermo.coupling_for_tc(T_c)
+    rho = 1.975 - margin
+    for _ in range(20):
+        p = cell_params(n, rho, Ra, T_c=T_c, **kw)
+        new = thermo.boiling_threshold_density(n, p.T_d, p.T_u, G, p.gravity) - margin
+        if abs(new - rho) < 1e-6:
+            break
+        rho = new
+    return rho
+
+
+def seeded_density(n, rho_mean, amp, seed):
+    import synth
+    return torch.from_numpy(synth.noisy_density(n, n, n, rho_mean, amp, seed)).cuda().reshape(-1)
+
+
+def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None):
+    """Run and record Nu_bot, Nu_top and the bulk-averaged Nu(z) every
+    diag_every steps; returns the record."""
+    lat = lbm.Lattice(p, rho0)
+    tot0 = lat.moments()
+    rec = {"t": [], "nu_bot": [], "nu_top": [], "nu_bulk": [], "mass_drift": [], "ok": True}
+    n = p.nz
+    bulk = slice(n // 4, 3 * n // 4)
+    step_ms = 0.0
+    t = 0
+    while t < steps:
+        k = min(diag_every, steps - t)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.h.stream)
+        lat.step(k)
+        e1.record(lat.h.stream)
+        torch.cuda.synchronize()
+        step_ms += e0.elapsed_time(e1)
+        t += k
+        try:
+            tot = lat.moments()
+        except lbm.LbmError as e:
+            rec["ok"] = False
+            rec["error"] = str(e)
+            break
+        nb, nt, nu_z, T_z = lat.nusselt()
+        rec["t"].append(t)
+        rec["nu_bot"].append(nb)
+        rec["nu_top"].append(nt)
+        rec["nu_bulk"].append(float(np.mean(nu_z[bulk])))
+        rec["mass_drift"].append(float(tot[0] / tot0[0] - 1))
+        if log:
+            print(json.dumps({"t": t, "nu_bot": round(nb, 4), "nu_top": round(nt, 4),
+                              "nu_bulk": round(rec["nu_bulk"][-1], 4)}), file=log, flush=True)
+    if rec["ok"]:
+        nb, nt, nu_z, T_z = lat.nusselt()
+        rec["T_z"] = [float(x) for x in T_z]
+        rec["nu_z"] = [float(x) for x in nu_z]
+    rec["ms_per_step"] = step_ms / max(t, 1)
+    rec["mlups"] = p.n / (rec["ms_per_step"] * 1e-3) / 1e6
+    rec["lattice"] = lat
+    return rec
+
+
+def profile_asymmetry(T_z, T_d, T_u):
+    """(T_centre - T_mean) / T_mean of the horizontal-mean profile (Fig. 2
+    inset; the paper quotes 1 % for boiling)."""
+    T_z = np.asarray(T_z)
+    n = len(T_z)
+    Tc = 0.5 * (T_z[n // 2 - 1] + T_z[n // 2]) if n % 2 == 0 else T_z[n // 2]
+    Tm = 0.5 * (T_d + T_u)
+    return float((Tc - Tm) / Tm)
+
+
+def phase_statistics(lat, bins=200):
+    """Density histogram peaks (vapour, liquid) and bubble volumes: 6-connected
+    components of rho < (rho_g + rho_l)/2, periodic in x and y."""
+    from scipy import ndimage
+    _, fields = lat.fields()
+    rho = fields[0].cpu().numpy()
+    hist, edges = np.histogram(rho, bins=bins)
+    centres = 0.5 * (edges[1:] + edges[:-1])
+    split = np.searchsorted(centres, 1.0)
+    rho_g = float(centres[np.argmax(hist[:split])]) if split > 0 and hist[:split].sum() > 0 else float("nan")
+    rho_l = float(centres[split + np.argmax(hist[split:])])
+    thr = 0.5 * (rho_g + rho_l) if math.isfinite(rho_g) else 1.0
+    mask = rho < thr
+    lab, nlab = ndimage.label(mask)
+    if nlab > 0:
+        # merge labels across the periodic x and y faces
+        parent = np.arange(nlab + 1)
+
+        def find(a):
+            while parent[a] != a:
+                parent[a] = parent[parent[a]]
+                a = parent[a]
+            return a
+
+        for a, b in ((lab[:, :, 0], lab[:, :, -1]), (lab[:, 0, :], lab[:, -1, :])):
+            m = (a > 0) & (b > 0)
+            for x, y in zip(a[m].ravel(), b[m].ravel()):
+                rx, ry = find(x), find(y)
+                if rx != ry:
+                    parent[max(rx, ry)] = min(rx, ry)
+        roots = np.array([find(i) for i in range(nlab + 1)])
+        vols = np.bincount(roots[lab.ravel()], minlength=nlab + 1)[1:]
+        vols = vols[vols > 0]
+    else:
+        vols = np.zeros(0, dtype=np.int64)
+    return {"rho_g": rho_g, "rho_l": rho_l, "vapour_fraction": float(mask.mean()),
+            "n_bubbles": int(len(vols)), "bubble_volumes": sorted(int(v) for v in vols)}
+
+
+def _summary(rec, p):
+    nb = np.asarray(rec["nu_bulk"])
+    half = len(nb) // 2
+    out = {k: v for k, v in rec.items() if k != "lattice"}
+    if len(nb):
+        out["nu_bulk_mean_2nd_half"] = float(nb[half:].mean())
+        out["nu_bulk_std_2nd_half"] = float(nb[half:].std())
+        out["nu_bot_mean_2nd_half"] = float(np.mean(rec["nu_bot"][half:]))
+        out["nu_top_mean_2nd_half"] = float(np.mean(rec["nu_top"][half:]))
+    if "T_z" in rec:
+        out["T_centre_minus_mean_rel"] = profile_asymmetry(rec["T_z"], p.T_d, p.T_u)
+    out["params"] = {f: getattr(p, f) for f in ("nx", "ny", "nz", "storage", "tau_nu", "tau_kappa",
+                                                 "G", "T_d", "T_u", "gravity", "c_v", "rho_kappa")}
+    out["params"]["rayleigh"] = getattr(p, "rayleigh", None)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["convection", "pair", "precision", "adjoint"])
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--rho", type=float, default=None,
+                    help="mean density of the boiling cell (default: from the hydrostatic column)")
+    ap.add_argument("--rho-single", type=float, default=2.49)
+    ap.add_argument("--ra", type=float, default=1e6)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--diag", type=int, default=500)
+    ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--seed", type=int, default=1234)
+    ap.add_argument("--noise", type=float, default=0.01)
+    ap.add_argument("--ckpt", type=int, default=20)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    lbm.load_library()
+    res = {}
+    log = sys.stderr
+    if a.rho is None:
+        a.rho = boiling_density(a.n, a.ra)
+    if a.what == "convection":
+        p = cell_params(a.n, a.rho, a.ra, a.storage)
+        rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log)
+        res = _summary(rec, p)
+        if rec["ok"]:
+            res["phases"] = phase_statistics(rec["lattice"])
+    elif a.what == "pair":
+        for name, rho in (("boiling", a.rho), ("single_phase", a.rho_single)):
+            p = cell_params(a.n, rho, a.ra, a.storage)
+            rec = convection(p, seeded_density(a.n, rho, a.noise, a.seed), a.steps, a.diag, log)
+            res[name] = _summary(rec, p)
+            if rec["ok"]:
+                res[name]["phases"] = phase_statistics(rec["lattice"])
+            del rec
+            torch.cuda.empty_cache()
+    elif a.what == "precision":
+        for st in ("fp32", "fp16dev", "bf16dev"):
+            p = cell_params(a.n, a.rho, a.ra, st)
+            rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log)
+            res[st] = _summary(rec, p)
+            if rec["ok"]:
+                res[st]["phases"] = phase_statistics(rec["lattice"])
+            del rec
+            torch.cuda.empty_cache()
+        if all(res[s].get("ok") for s in res):
+            ref = np.asarray(res["fp32"]["nu_bulk"])
+            for st in ("fp16dev", "bf16dev"):
+                x = np.asarray(res[st]["nu_bulk"])
+                res[st]["nu_bulk_max_abs_diff_vs_fp32"] = float(np.abs(x - ref).max())
+    elif a.what == "adjoint":
+        from dataclasses import replace
+
+        from . import adjoint
+        import synth
+        out = {}
+        d = torch.from_numpy(synth.random_unit_field(a.n, a.n, a.n, 7)).cuda().reshape(-1)
+        for st in ("fp32", "fp64"):
+            p = cell_params(a.n, a.rho, a.ra, st)
+            rho0 = seeded_density(a.n, a.rho, a.noise, a.seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J, dr, dTd, dG = adjoint.heat_flux_gradients(p, rho0, a.steps, a.ckpt)
+            torch.cuda.synchronize()
+            out[st] = {"J": J, "dJ_dTd": dTd, "dJ_dG": dG, "dJ_drho0_dir": float((dr * d).sum()),
+                       "seconds": time.perf_counter() - t0}
+            print(json.dumps({st: out[st]}), file=log, flush=True)
+        for k in ("dJ_dTd", "dJ_dG", "dJ_drho0_dir"):
+            out[f"fp32_vs_fp64_rel_{k}"] = abs(out["fp32"][k] / out["fp64"][k] - 1)
+        # central differences of the FP64 forward, initial T profile held fixed
+        p = cell_params(a.n, a.rho, a.ra, "fp64")
+        rho0 = seeded_density(a.n, a.rho, a.noise, a.seed)
+        T0 = adjoint.conduction_profile(p)
+
+        def J_of(q, r):
+            return adjoint.heat_flux_objective(q, r, a.steps, T0)
+
+        h = 1e-4 * p.T_d
+        fd_Td = (J_of(replace(p, T_d=p.T_d + h), rho0) - J_of(replace(p, T_d=p.T_d - h), rho0)) / (2 * h)
+        h = 1e-4 * abs(p.G)
+        fd_G = (J_of(replace(p, G=p.G + h), rho0) - J_of(replace(p, G=p.G - h), rho0)) / (2 * h)
+        h = 1e-4 * float(rho0.abs().max())
+        fd_r = (J_of(p, rho0 + h * d) - J_of(p, rho0 - h * d)) / (2 * h)
+        out["fd_fp64"] = {"dJ_dTd": fd_Td, "dJ_dG": fd_G, "dJ_drho0_dir": fd_r}
+        for st in ("fp64", "fp32"):
+            for k in ("dJ_dTd", "dJ_dG", "dJ_drho0_dir"):
+                out[f"{st}_vs_fd_rel_{k}"] = abs(out[st][k] / out["fd_fp64"][k] - 1)
+        out["params"] = {"n": a.n, "steps": a.steps, "ckpt": a.ckpt, "rho_mean": a.rho,
+                         "gravity": p.gravity, "G": p.G, "T_d": p.T_d, "T_u": p.T_u,
+                         "tau_nu": p.tau_nu, "tau_kappa": p.tau_kappa}
+        res = out
+    js = json.dumps(res)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(js)
+    print(js[:2000])
+
+
+if __name__ == "__main__":
+    main()
