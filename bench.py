@@ -1,20 +1,21 @@
 """Throughput of the thermal pseudopotential D3Q19 step on one MI355X.
 
 Workload: the 512^3 boiling convection cell in FP32 (walls at z, periodic x, y;
-mean density inside the coexistence region at the bottom-wall temperature),
-the paper's resolution (L = 512, Table 1).  A step is one full lattice update
+Ra = 1e7, Pr = 9, nu = 0.0165; mean density such that the bottom layer of the
+hydrostatic liquid column lies past the liquid spinodal), the paper's
+resolution (L = 512, Table 1).  A step is one full lattice update
 (every step of the hot path: moments, pseudopotential and thermal forces,
 both BGK collisions with the counter-term, streaming and the walls) with the
 populations resident in HBM.
 
 Prints one JSON line: MLUPS, ms per step, the roofline of the step kernel
-(algorithmic bytes = 38 reads + 38 writes of stored populations per node),
+(algorithmic bytes = one read and one write of each node's stored
+populations: 2 x 152 B in FP32, 2 x 88 B in the 16-bit forms),
 the FP16/BF16-deviation storage forms beside it, and the FP64 CPU oracle
 timed on a bounded sample on the host.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -24,22 +25,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + achieved HBM GB/s (% of peak), FP32 vs FP16-storage, 512^3 boiling"
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2}
+# bytes of one node's populations in one buffer (read once, written once per step)
+NODE_BYTES = {"fp64": 19 * 16, "fp32": 19 * 8, "fp16dev": 18 * 4 + 16, "bf16dev": 18 * 4 + 16}
 
-TC = 0.05                              # critical temperature (sets G)
-NU = 0.0165                            # kinematic viscosity, Table 1
-TAU_NU = 0.5 + 3 * NU                  # 0.5495
-TAU_KAPPA = 0.6417                     # Pr = 9 in the liquid at the mid temperature
-RHO_BOIL = 1.93                        # liquid-rich mean density, boils at the bottom wall
-GRAVITY = 3.2e-6
+RA = 1e7                               # Rayleigh number of the boiling cell (Table 1 order)
 
 
 def workload_params(lbm, n, storage, kernel=0, tile_y=0, z_chunk=0, tile_x=0):
-    return lbm.Params(
-        n, n, n, storage=lbm.STORAGE[storage], kernel=kernel, tile_x=tile_x, tile_y=tile_y,
-        z_chunk=z_chunk,
-        tau_nu=TAU_NU, tau_kappa=TAU_KAPPA, G=-TC * math.e ** 2, T_d=0.95 * TC, T_u=0.85 * TC,
-        gravity=GRAVITY, c_v=1.0, rho_kappa=0.5, rho_ref=RHO_BOIL, T_ref=0.9 * TC)
+    """The boiling convection cell of side n: T_c = 0.12, T_d = 0.95 T_c,
+    T_u = 0.85 T_c, nu = 0.0165, Pr = 9 in the liquid, gravity from Ra, mean
+    density from the hydrostatic liquid column (bottom layer past the liquid
+    spinodal)."""
+    from paper_1111_0905_amd import experiments
+    rho = experiments.boiling_density(n, RA)
+    return experiments.cell_params(n, rho, RA, storage, kernel=kernel, tile_x=tile_x,
+                                   tile_y=tile_y, z_chunk=z_chunk)
+
+
+def seeded_density(n, rho_mean):
+    import synth
+    return synth.noisy_density(n, n, n, rho_mean, 0.01, 1234)
 
 
 def time_steps(lat, steps, warmup):
@@ -65,7 +70,7 @@ def run_storage(lbm, n, storage, steps, warmup, rho0, kernel=0, tile_y=0, z_chun
     ms, wall = time_steps(lat, steps, warmup)
     tot = lat.moments()          # also checks the state is finite
     nodes = n ** 3
-    bpn = 2 * 38 * BYTES_PER_POP[storage]
+    bpn = 2 * NODE_BYTES[storage]
     res = {
         "mlups": nodes / (ms * 1e-3) / 1e6,
         "ms_per_step": ms,
@@ -106,14 +111,16 @@ def measured_traffic(storage, n):
 def cpu_baseline(seconds=15.0):
     """FP64 oracle on the host, 64^3 sample of the same physics."""
     import torch
-    import synth
     from oracle import lbm as olbm
     threads = os.cpu_count() or 1
     torch.set_num_threads(threads)
+    from paper_1111_0905_amd import lbm
     n = 64
-    p = olbm.Params(n, n, n, tau_nu=TAU_NU, tau_kappa=TAU_KAPPA, G=-TC * math.e ** 2,
-                    T_d=0.95 * TC, T_u=0.85 * TC, gravity=GRAVITY)
-    o = olbm.Oracle(p, synth.noisy_density(n, n, n, RHO_BOIL, 0.01, 1234))
+    w = workload_params(lbm, 512, "fp32")      # physics of the full-size cell
+    p = olbm.Params(n, n, n, tau_nu=w.tau_nu, tau_kappa=w.tau_kappa, G=w.G, T_d=w.T_d,
+                    T_u=w.T_u, gravity=w.gravity, c_v=w.c_v, rho_kappa=w.rho_kappa,
+                    T_lat=w.T_lat)
+    o = olbm.Oracle(p, seeded_density(n, w.rho_ref))
     o.step(1)
     steps = 0
     t0 = time.perf_counter()
@@ -169,18 +176,18 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
     from paper_1111_0905_amd import lbm
 
     lbm.load_library()
     n = args.size
     print(f"bench: generating {n}^3 seeded density field", file=sys.stderr, flush=True)
-    rho0 = torch.from_numpy(synth.noisy_density(n, n, n, RHO_BOIL, 0.01, 1234)).cuda().reshape(-1)
+    rho_mean = workload_params(lbm, n, "fp32").rho_ref
+    rho0 = torch.from_numpy(seeded_density(n, rho_mean)).cuda().reshape(-1)
 
     if args.sweep:
-        combos = [(0, 32, 16), (2, 64, 16), (0, 64, 8)]
+        combos = [(0, 32, 16), (2, 64, 16), (2, 64, 8), (0, 64, 8), (2, 32, 16), (0, 32, 16)]
         for kernel, tx, ty in combos:
-            for zc in (0, 256, 128):
+            for zc in (0,):
                 r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
                                    kernel, ty, zc, tx)
                 print(json.dumps({"kernel": kernel, "tile": [tx, ty], "z_chunk": zc,

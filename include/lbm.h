@@ -54,7 +54,15 @@
 extern "C" {
 #endif
 
-/* storage of the populations; arithmetic is FP64 for LBM_FP64, FP32 else */
+/* storage of the populations; arithmetic is FP64 for LBM_FP64, FP32 else.
+ * Bytes per node and buffer: FP64 304, FP32 152, the 16-bit forms 88: the 18
+ * moving (f_l, g_l) pairs as 16-bit deviations from the reference pops
+ * (round to nearest even), the rest pair in FP64.  The 16-bit forms update
+ * the rest pair in remainder form: old value + what the moving pairs gave up
+ * in the collision + the rounding residuals of their stores (+ the energy
+ * source for g), so the stored mass is conserved to the rounding of small
+ * per-node sums, not drifting with the rounding of f_0 (which carries most
+ * of the mass). */
 enum {
   LBM_FP64 = 0,      /* double storage, double arithmetic */
   LBM_FP32 = 1,      /* float storage, float arithmetic */
@@ -106,7 +114,9 @@ typedef struct lbm_params {
   int32_t kernel;
   int32_t tile_x;      /* fused-kernel tile width: 0 (default 64), 32 or 64 */
   int32_t tile_y;      /* fused-kernel tile height: 0 (default), 1..32, see lbm_init */
-  int32_t z_chunk;     /* planes per fused-kernel work-group column (0 = default) */
+  int32_t z_chunk;     /* planes per fused-kernel work-group column; 0 = the whole
+                          height, split into chunks of at least 4 planes when
+                          the lattice is too small to give about 16 waves per CU */
   int32_t adjoint;     /* 1 = reserve workspace for the lbm_adjoint_* entry points */
   double tau_nu, tau_kappa;
   double G;
@@ -182,10 +192,12 @@ int lbm_set_state(lbm_handle* h, const double* state);
 
 /*
  * Discrete adjoint (reverse mode) of one step, for gradients of objectives of
- * the trajectory (SURVEY's differentiation form; the step is eqs. (LBEQ)/(LBEQ2)
- * with everything of the Algorithm section, so its transposed Jacobian is
- * exact up to rounding).  Needs a handle made with adjoint = 1; arithmetic in
- * the handle's compute precision (FP64 for LBM_FP64, else FP32).
+ * the trajectory (the step is eqs. (LBEQ)/(LBEQ2) with everything of the
+ * Algorithm section, so its transposed Jacobian is exact up to rounding).
+ * Needs a handle made with adjoint = 1 (which adds 88 bytes per node of
+ * workspace).  The arithmetic is FP64 for every storage form: the adjoint
+ * linearises the FP64 step about the given state, which for a reduced-precision
+ * handle is a state of its own (rounded) trajectory.
  *   state:   device, canonical FP64 state s_t (the input of the step t -> t+1);
  *   adj_in:  device, 38*N doubles, lambda_{t+1} = dJ/ds_{t+1};
  *   adj_out: device, 38*N doubles, receives lambda_t = (ds_{t+1}/ds_t)^T lambda_{t+1}

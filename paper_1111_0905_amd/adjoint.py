@@ -9,7 +9,10 @@ half-cell wall difference) averaged over the trajectory s_1..s_{N_t} of the
 step of eqs. (LBEQ)/(LBEQ2) from the local equilibrium of (rho0, T0).
 Gradients with respect to T_d (through the bottom-wall rule and q_bot; the
 initial T0 is held fixed), G (eq. (FORCE)) and the initial density field
-rho0.
+rho0.  The lattice temperature T_lat of the split ideal pressure is a
+numerical constant of the scheme and is held fixed too; when it is left at 0
+the library sets it to (T_d + T_u)/2, so a finite-difference check in T_d
+passes T_lat explicitly.
 
 The forward pass keeps a canonical FP64 checkpoint every `ckpt_every`
 steps; the backward pass restores each checkpoint, recomputes its segment

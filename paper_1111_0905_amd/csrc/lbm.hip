@@ -3,7 +3,9 @@
 // The ABI is declared and documented in include/lbm.h.
 //
 // Data layout in HBM: structure of arrays of pairs: word l of node (i, j, k)
-// holds (f_l, g_l) at l * N + (k * ny + j) * nx + i (i fastest); two
+// holds (f_l, g_l) at l * N + (k * ny + j) * nx + i (i fastest) for FP64 and
+// FP32; the 16-bit forms keep the rest pair in FP64 ahead of the 18 moving
+// rows (see the codecs in physics.hpp); two
 // ping-pong buffers hold the post-streaming populations.  Streaming is a push: the collided value of
 // node x in direction l is written to x + c_l of the other buffer; at the
 // walls it is written back to x in direction opp(l) (half-way bounce-back for
@@ -56,31 +58,54 @@ __device__ __forceinline__ uint32_t node_off(int i, int j, int k, int nx, int ny
 }
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// Push-stream the collided values of node (i, j, k) into `out`.
+// Push-stream the collided values of node (i, j, k) into `out`: operator()
+// for the moving directions, then rest() for the rest pair, which stays at
+// the node.
 template <typename C, typename R = typename C::R>
 struct Streamer {
+  using T0 = typename Codec<C>::T0;
   typename C::S* out;
+  const typename C::S* in;   // this step's input (the rest pair is re-read from it)
   const DevParams<R>& P;
   size_t N;
   int i, j, k, im, ip, jm, jp;
-  __device__ __forceinline__ void operator()(int l, R fs, R gs) const {
+  // what the moving pairs gave up: the collision increments plus (stored
+  // value - decoded stored value), summed over the 18 directions
+  R rf = R(0), rg = R(0);
+  // fs, gs: collided values of direction l; df, dg: what the collision took
+  // from the pair (f_l - fs up to the rounding of fs)
+  __device__ __forceinline__ void operator()(int l, R fs, R gs, R df, R dg) {
+    if constexpr (Codec<C>::kResidual) {
+      rf += df;
+      rg += dg;
+    }
     const int nz = P.nz;
     int kk = k + CZ[l];
     const int ii = CX[l] > 0 ? ip : (CX[l] < 0 ? im : i);
     const int jj = CY[l] > 0 ? jp : (CY[l] < 0 ? jm : j);
     if (kk >= 0 && kk < nz) {
-      const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)l * N, o, fs, gs, P.fref[l], P.gref[l]);
+      store_moving<C>(out, l, N, node_off(ii, jj, kk, P.nx, P.ny), fs, gs, P.fref[l], P.gref[l],
+                      rf, rg);
     } else if (P.periodic_z) {
       kk = kk < 0 ? kk + nz : kk - nz;
-      const uint32_t o = node_off(ii, jj, kk, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)l * N, o, fs, gs, P.fref[l], P.gref[l]);
+      store_moving<C>(out, l, N, node_off(ii, jj, kk, P.nx, P.ny), fs, gs, P.fref[l], P.gref[l],
+                      rf, rg);
     } else {  // the wall sends it back into this node in the opposite direction
       const R Tw = kk < 0 ? P.T_d : P.T_u;
       const int q = OPP[l];
-      const uint32_t o = node_off(i, j, k, P.nx, P.ny);
-      Codec<C>::st(out + (size_t)q * N, o, fs, -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw,
-                   P.fref[OPP[l]], P.gref[OPP[l]]);
+      store_moving<C>(out, q, N, node_off(i, j, k, P.nx, P.ny), fs,
+                      -gs + R(2) * wlat<R>(l) * P.rho_kappa * Tw, P.fref[q], P.gref[q], rf, rg);
+    }
+  }
+  // fs, gs: the BGK values of the rest pair; S: the node's energy source
+  __device__ __forceinline__ void rest(R fs, R gs, R S) {
+    const uint32_t o = node_off(i, j, k, P.nx, P.ny);
+    if constexpr (Codec<C>::kResidual) {  // remainder form: mass kept, energy + S
+      T0 f0, g0;
+      Codec<C>::ld0(in, o, f0, g0);
+      Codec<C>::st0(out, o, f0 + (T0)rf, g0 + (T0)(S + rg));
+    } else {
+      Codec<C>::st0(out, o, fs, gs);
     }
   }
 };
@@ -89,7 +114,29 @@ template <typename C, typename R = typename C::R>
 __device__ __forceinline__ void load_node(const typename C::S* __restrict__ in, size_t N, uint32_t o,
                                           const DevParams<R>& P, R* f, R* g) {
 #pragma unroll
-  for (int l = 0; l < Q; ++l) Codec<C>::ld(in + (size_t)l * N, o, f[l], g[l], P.fref[l], P.gref[l]);
+  for (int l = 0; l < Q; ++l) load_pair<C>(in, l, N, o, f[l], g[l], P.fref[l], P.gref[l]);
+}
+
+// Store all pairs of node o in place (no streaming) from FP64 values; the
+// 16-bit forms add the rounding residuals of the moving pairs (taken in FP64)
+// to the rest pair, so the stored sums equal the given ones.
+template <typename C, typename R = typename C::R>
+__device__ __forceinline__ void store_node(typename C::S* out, size_t N, uint32_t o,
+                                           const DevParams<R>& P, const double* f, const double* g) {
+  using T0 = typename Codec<C>::T0;
+  double rf = 0.0, rg = 0.0;
+#pragma unroll
+  for (int l = 1; l < Q; ++l) {
+    const typename C::S w = Codec<C>::enc((R)f[l], (R)g[l], P.fref[l], P.gref[l]);
+    at32(Codec<C>::row(out, l, N), o) = w;
+    if constexpr (Codec<C>::kResidual) {
+      R fd, gd;
+      Codec<C>::dec(w, fd, gd, P.fref[l], P.gref[l]);
+      rf += f[l] - (double)fd;
+      rg += g[l] - (double)gd;
+    }
+  }
+  Codec<C>::st0(out, o, (T0)(f[0] + rf), (T0)(g[0] + rg));
 }
 
 // ---------------------------------------------------------------- init / state
@@ -107,11 +154,9 @@ __global__ void k_init(typename C::S* out, const double* __restrict__ rho0,
     } else {  // conduction profile between the half-way walls
       T = (R)((double)P.T_d + ((double)P.T_u - (double)P.T_d) * ((double)k + 0.5) / (double)P.nz);
     }
-    R f[Q], g[Q];
-    rest_equilibrium<R>((R)rho0[n], T, P, f, g);
-#pragma unroll
-    for (int l = 0; l < Q; ++l)
-      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, f[l], g[l], P.fref[l], P.gref[l]);
+    double f[Q], g[Q];
+    rest_equilibrium<double>(rho0[n], (double)T, (double)P.rho_kappa, (double)P.T_lat, f, g);
+    store_node<C>(out, N, (uint32_t)n, P, f, g);
   }
 }
 
@@ -123,8 +168,12 @@ __global__ void k_get_state(const typename C::S* __restrict__ in, double* __rest
        n += (size_t)gridDim.x * blockDim.x) {
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(in, (uint32_t)n, f0, g0);
+    st[n] = (double)f0;
+    st[(size_t)Q * N + n] = (double)g0;
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
+    for (int l = 1; l < Q; ++l) {
       st[(size_t)l * N + n] = (double)f[l];
       st[(size_t)(l + Q) * N + n] = (double)g[l];
     }
@@ -136,10 +185,13 @@ __global__ void k_set_state(typename C::S* out, const double* __restrict__ st, D
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
+    double f[Q], g[Q];
 #pragma unroll
-    for (int l = 0; l < Q; ++l)
-      Codec<C>::st(out + (size_t)l * N, (uint32_t)n, (R)st[(size_t)l * N + n],
-                   (R)st[(size_t)(l + Q) * N + n], P.fref[l], P.gref[l]);
+    for (int l = 0; l < Q; ++l) {
+      f[l] = st[(size_t)l * N + n];
+      g[l] = st[(size_t)(l + Q) * N + n];
+    }
+    store_node<C>(out, N, (uint32_t)n, P, f, g);
   }
 }
 
@@ -218,7 +270,7 @@ __global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* _
     load_node<C>(in, N, (uint32_t)n, P, f, g);
     ScratchNb<R> nb{srho, sE, P, i, j, k};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
-    Streamer<C> em{out, P, N, i, j, k, wrap(i - 1, P.nx), wrap(i + 1, P.nx),
+    Streamer<C> em{out, in, P, N, i, j, k, wrap(i - 1, P.nx), wrap(i + 1, P.nx),
                    wrap(j - 1, P.ny), wrap(j + 1, P.ny)};
     collide<R>(f, g, m, P, em);
   }
@@ -292,16 +344,23 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
   using S = typename C::S;
   // the own node's stored words of plane kp go to w (KEEP) and are decoded
   // again when the plane is collided; this keeps the 16-bit forms packed
-  auto fill = [&](int kp, int s, S* w) {
+  using T0 = typename Codec<C>::T0;
+  auto fill = [&](int kp, int s, S* w, T0& w0f, T0& w0g) {
     if (active) {
       const uint32_t o = node_off(i, j, kp, nx, ny);
-      R rho = R(0), E = R(0);
+      T0 f0, g0;
+      Codec<C>::ld0(in, o, f0, g0);
+      if (KEEP) {
+        w0f = f0;
+        w0g = g0;
+      }
+      R rho = (R)f0, E = (R)g0;
 #pragma unroll
-      for (int l = 0; l < Q; ++l) {
-        const S v = at32(in + (size_t)l * N, o);
+      for (int l = 1; l < Q; ++l) {
+        const S v = at32(Codec<C>::row(in, l, N), o);
         if (KEEP) w[l] = v;
         R f, g;
-        Unpack<C>::run(v, f, g, P.fref[l], P.gref[l]);
+        Codec<C>::dec(v, f, g, P.fref[l], P.gref[l]);
         rho += f;
         E += g;
       }
@@ -331,20 +390,21 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
     }
   };
 
-  S wa[Q], wb[Q];
+  S wa[Q], wb[Q];             // raw words of the moving pairs (KEEP); [0] unused
+  T0 wa0f, wa0g, wb0f, wb0g;  // the rest pair (KEEP)
   const bool walls = !P.periodic_z;
   if (k0 > 0)
-    fill(k0 - 1, slot(k0 - 1), wb);
+    fill(k0 - 1, slot(k0 - 1), wb, wb0f, wb0g);
   else if (!walls)
-    fill(nz - 1, slot(k0 - 1), wb);
-  fill(k0, slot(k0), wa);
+    fill(nz - 1, slot(k0 - 1), wb, wb0f, wb0g);
+  fill(k0, slot(k0), wa, wa0f, wa0g);
 
   for (int k = k0; k < k1; ++k) {
     const int kn = k + 1;
     if (kn < nz)
-      fill(kn, slot(kn), wb);
+      fill(kn, slot(kn), wb, wb0f, wb0g);
     else if (!walls)
-      fill(0, slot(kn), wb);
+      fill(0, slot(kn), wb, wb0f, wb0g);
     __syncthreads();
     if (walls && (k == 0 || kn == nz)) {
       if (k == 0) ghost(slot(-1), slot(0), slot(1));
@@ -353,12 +413,20 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
     }
     if (active) {
       R fa[Q], ga[Q];
+      T0 f0, g0;
       if (KEEP) {
+        f0 = wa0f;
+        g0 = wa0g;
 #pragma unroll
-        for (int l = 0; l < Q; ++l) Unpack<C>::run(wa[l], fa[l], ga[l], P.fref[l], P.gref[l]);
+        for (int l = 1; l < Q; ++l) Codec<C>::dec(wa[l], fa[l], ga[l], P.fref[l], P.gref[l]);
       } else {
-        load_node<C>(in, N, node_off(i, j, k, nx, ny), P, fa, ga);
+        const uint32_t o = node_off(i, j, k, nx, ny);
+        Codec<C>::ld0(in, o, f0, g0);
+#pragma unroll
+        for (int l = 1; l < Q; ++l) load_pair<C>(in, l, N, o, fa[l], ga[l], P.fref[l], P.gref[l]);
       }
+      fa[0] = (R)f0;
+      ga[0] = (R)g0;
       const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
       auto at = [&](const R(*A)[PN], int l) {
         const int s = CZ[l] < 0 ? sm : (CZ[l] > 0 ? sp : s0);
@@ -370,12 +438,14 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       grad_w<R>([&](int l) { return at(sRho, l); }, grx, gry, grz);
       const Macro<R> m = node_macro<R>(fa, ga, sRho[s0][own_s], sE[s0][own_s], sPsi[s0][own_s],
                                        gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
-      Streamer<C> em{out, P, N, i, j, k, im, ip, jm, jp};
+      Streamer<C> em{out, in, P, N, i, j, k, im, ip, jm, jp};
       collide<R>(fa, ga, m, P, em);
     }
     if (KEEP) {
+      wa0f = wb0f;
+      wa0g = wb0g;
 #pragma unroll
-      for (int l = 0; l < Q; ++l) wa[l] = wb[l];
+      for (int l = 1; l < Q; ++l) wa[l] = wb[l];
     }
   }
 }
@@ -415,13 +485,24 @@ __global__ __launch_bounds__(256) void k_diag(const typename C::S* __restrict__ 
     load_node<C>(in, N, (uint32_t)n, P, f, g);
     ScratchNb<R> nb{srho, sE, P, i, j, k};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
-    const double rho = m.rho, T = m.T;
+    // mass and energy sums of the stored populations in FP64 (the FP32 node
+    // sums of the compute path round the same way at nodes of equal state,
+    // which would bias a global sum)
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(in, (uint32_t)n, f0, g0);
+    double rho = (double)f0, E = (double)g0;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      rho += (double)f[l];
+      E += (double)g[l];
+    }
+    const double T = E / rho;
     const double U = c_v * T + 0.25 * G * exp(-2.0 / rho);
     acc[0] += rho;
     acc[1] += rho * (double)m.vx;
     acc[2] += rho * (double)m.vy;
     acc[3] += rho * (double)m.vz;
-    acc[4] += (double)m.E;
+    acc[4] += E;
     acc[5] += rho * U;
     const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite((double)m.vx) ||
                      !isfinite((double)m.vy) || !isfinite((double)m.vz);
@@ -789,13 +870,16 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // bytes of one stored population (a stored word holds the pair f_l, g_l)
-size_t storage_bytes(int storage) {
+// Bytes of one node's populations in one buffer, and of the widest row (one
+// direction's array), which must stay below 4 GiB for the 32-bit offsets.
+size_t node_bytes(int storage) {
   switch (storage) {
-    case LBM_FP64: return 8;
-    case LBM_FP32: return 4;
-    default: return 2;
+    case LBM_FP64: return Q * 16;
+    case LBM_FP32: return Q * 8;
+    default: return (Q - 1) * 4 + 16;   // 18 moving 16-bit pairs + the FP64 rest pair
   }
 }
+size_t row_bytes(int storage) { return storage == LBM_FP32 ? 8 : 16; }
 size_t real_bytes(int storage) { return storage == LBM_FP64 ? 8 : 4; }
 
 constexpr int kDiagBlocks = 1024;
@@ -804,8 +888,8 @@ int validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
   if (!p->periodic_z && p->nz < 2) return fail(LBM_EINVAL, "walls need nz >= 2");
-  if ((double)p->nx * p->ny * p->nz * 2.0 * (double)storage_bytes(p->storage) >= 4294967296.0)
-    return fail(LBM_EINVAL, "lattice too large (one population-pair array must stay below 4 GiB)");
+  if ((double)p->nx * p->ny * p->nz * (double)row_bytes(p->storage) >= 4294967296.0)
+    return fail(LBM_EINVAL, "lattice too large (one direction's population array must stay below 4 GiB)");
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16DEV) return fail(LBM_EINVAL, "unknown storage");
   if (p->kernel != LBM_KERNEL_FUSED && p->kernel != LBM_KERNEL_REFERENCE &&
       p->kernel != LBM_KERNEL_FUSED_RELOAD)
@@ -836,12 +920,14 @@ struct Layout {
 Layout layout(const lbm_params* p) {
   Layout L;
   L.N = (size_t)p->nx * p->ny * p->nz;
-  L.pop_bytes = align_up(2 * Q * L.N * storage_bytes(p->storage));
+  L.pop_bytes = align_up(L.N * node_bytes(p->storage));
   L.buf = L.pop_bytes;
   L.scr = align_up(L.N * real_bytes(p->storage));
   L.part = align_up((size_t)kDiagBlocks * 8 * sizeof(double));
   L.small = align_up((size_t)(16 + 4 * p->nz) * sizeof(double));
-  L.adj = p->adjoint ? align_up((size_t)9 * L.N * real_bytes(p->storage)) : 0;
+  // adjoint scratch, FP64 for every storage form: 9 gradient-adjoint
+  // components plus rho and E of the forward state
+  L.adj = p->adjoint ? align_up((size_t)11 * L.N * sizeof(double)) : 0;
   L.total = 2 * L.buf + 2 * L.scr + L.part + 2 * L.small + L.adj;
   return L;
 }
@@ -859,7 +945,9 @@ struct lbm_handle {
   double* partials;
   double* small;   // totals / nusselt results
   double* prof;    // plane profiles (2 nz)
-  void* gbar;      // adjoint scratch (9 N reals) or NULL
+  double* gbar;    // adjoint scratch (9 N doubles) or NULL
+  double* arho;    // rho and E of the state the adjoint step linearises about
+  double* aE;
   int cur;
   int64_t t;
   int kernel, tile_x, tile_y, z_chunk;
@@ -1071,14 +1159,14 @@ int do_adjoint_step(lbm_handle* h, const double* st, const double* lam1, double*
   const DevParams<R> P = dev_params<R>(h->p);
   const size_t N = h->L.N;
   hipLaunchKernelGGL((k_adj_rhoE<R>), dim3(grid_for(N, 256)), dim3(256), 0, h->stream, st,
-                     (R*)h->srho, (R*)h->sE, P);
+                     (R*)h->arho, (R*)h->aE, P);
   HIP_TRY(hipGetLastError());
   const int nblk = std::min(kDiagBlocks, grid_for(N, 256));
   hipLaunchKernelGGL((k_adj_local<R>), dim3(nblk), dim3(256), 0, h->stream, st, lam1, lam0,
-                     (const R*)h->srho, (const R*)h->sE, (R*)h->gbar, P, h->partials);
+                     (const R*)h->arho, (const R*)h->aE, (R*)h->gbar, P, h->partials);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL((k_adj_stencil<R>), dim3(grid_for(N, 256)), dim3(256), 0, h->stream,
-                     (const R*)h->srho, (const R*)h->gbar, lam0, P);
+                     (const R*)h->arho, (const R*)h->gbar, lam0, P);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
   HIP_TRY(hipGetLastError());
@@ -1187,12 +1275,13 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->partials = (double*)c; c += L.part;
   h->small = (double*)c; c += L.small;
   h->prof = (double*)c; c += L.small;
-  h->gbar = L.adj ? (void*)c : nullptr;
+  h->gbar = L.adj ? (double*)c : nullptr;
+  h->arho = L.adj ? h->gbar + 9 * L.N : nullptr;
+  h->aE = L.adj ? h->gbar + 10 * L.N : nullptr;
   h->cur = 0;
   h->t = 0;
   // defaults from tile/variant sweeps at 512^3 on MI355X: FP32 keeps the next
-  // plane in registers on 32 x 16 tiles; the 16-bit forms re-read it from
-  // cache on 64 x 16 tiles (four waves per SIMD)
+  // plane in registers on 32 x 16 tiles, the 16-bit forms on 64 x 8 tiles
   h->kernel = p->kernel;
   if (p->tile_x == 0 && p->tile_y == 0) {
     if (p->storage == LBM_FP64) {
@@ -1203,14 +1292,27 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
       h->tile_y = 16;
     } else {
       h->tile_x = 64;
-      h->tile_y = 16;
-      if (p->kernel == LBM_KERNEL_FUSED) h->kernel = LBM_KERNEL_FUSED_RELOAD;
+      h->tile_y = 8;
     }
   } else {
     h->tile_x = p->tile_x ? p->tile_x : 64;
     h->tile_y = p->tile_y ? p->tile_y : 8;
   }
-  h->z_chunk = p->z_chunk ? std::min(p->z_chunk, p->nz) : std::min(512, p->nz);
+  if (p->z_chunk) {
+    h->z_chunk = std::min(p->z_chunk, p->nz);
+  } else {
+    // split the z columns until the launch holds about 16 waves per compute
+    // unit (256 CUs); every chunk re-reads one halo plane on each side, so
+    // chunks stay at least 4 planes deep
+    const long long tiles = (long long)((p->nx + h->tile_x - 1) / h->tile_x) *
+                            ((p->ny + h->tile_y - 1) / h->tile_y);
+    const long long waves = tiles * ((h->tile_x * h->tile_y + 63) / 64);
+    const long long want = 16LL * 256;
+    const long long nzc = std::max(1LL, (want + waves - 1) / waves);
+    int zc = (int)((p->nz + nzc - 1) / nzc);
+    zc = std::max(zc, 4);
+    h->z_chunk = std::min(zc, p->nz);
+  }
   rc = dispatch<InitFn>(p->storage, h, rho0, T0);
   if (rc == LBM_OK) {
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -1265,22 +1367,19 @@ int lbm_adjoint_step(lbm_handle* h, const double* state, const double* adj_in, d
   if (!h || !state || !adj_in || !adj_out) return fail(LBM_EINVAL, "NULL argument");
   if (!h->gbar) return fail(LBM_EINVAL, "handle was created without adjoint = 1");
   if (adj_in == adj_out) return fail(LBM_EINVAL, "adj_in and adj_out must not alias");
-  return h->p.storage == LBM_FP64 ? do_adjoint_step<double>(h, state, adj_in, adj_out, grads)
-                                  : do_adjoint_step<float>(h, state, adj_in, adj_out, grads);
+  return do_adjoint_step<double>(h, state, adj_in, adj_out, grads);
 }
 
 int lbm_adjoint_qbot(lbm_handle* h, const double* state, double weight, double* adj, double* q,
                      double* grads) {
   if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
   if (h->p.periodic_z) return fail(LBM_EINVAL, "the wall heat flux needs walls");
-  return h->p.storage == LBM_FP64 ? do_adjoint_qbot<double>(h, state, weight, adj, q, grads)
-                                  : do_adjoint_qbot<float>(h, state, weight, adj, q, grads);
+  return do_adjoint_qbot<double>(h, state, weight, adj, q, grads);
 }
 
 int lbm_adjoint_init_rho(lbm_handle* h, const double* adj0, const double* T0, double* dJ_drho0) {
   if (!h || !adj0 || !dJ_drho0) return fail(LBM_EINVAL, "NULL argument");
-  return h->p.storage == LBM_FP64 ? do_adjoint_init<double>(h, adj0, T0, dJ_drho0)
-                                  : do_adjoint_init<float>(h, adj0, T0, dJ_drho0);
+  return do_adjoint_init<double>(h, adj0, T0, dJ_drho0);
 }
 
 void lbm_destroy(lbm_handle* h) { delete h; }

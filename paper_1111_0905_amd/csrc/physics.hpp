@@ -69,7 +69,22 @@ struct DevParams {
 // Populations are stored in pairs: word l of a node holds (f_l, g_l), so one
 // load or store moves both populations of a direction (push streaming sends
 // f*_l and g*_l to the same node, also at the walls).  Stored as S, computed
-// in R.  The 16-bit forms store (pop - pop_ref) and round to nearest even.
+// in R.  Buffer layout, structure of arrays (N nodes, node offset i):
+//   FP64, FP32:  direction l at words [l N, (l + 1) N).
+//   FP16, BF16:  the rest pair (l = 0) in FP64 (absolute values, N double2
+//                in 32-bit words [0, 4 N)); the 18 moving directions hold
+//                (pop - pop_ref) rounded to nearest even, direction l >= 1
+//                at words [(l + 3) N, (l + 4) N).
+// The rest population carries most of the mass (f_0 = rho (1 - 2 T_lat)),
+// and the decoded moving populations take few distinct values, so FP32
+// rounding of the node sums and of f_0 is correlated between nodes and steps
+// and would make mass drift.  The 16-bit forms therefore update the rest
+// pair in the remainder form: the new rest value is the old one plus what
+// the 18 moving pairs gave up in the collision plus the rounding residuals
+// of their 16-bit stores (plus the energy source S for g), accumulated in
+// FP32 from small terms and added in FP64 (Streamer::rest).  Stored mass is
+// then conserved to the rounding of those small sums, and the stored energy
+// changes exactly by S and the wall exchange.
 struct F64 { using S = double2; using R = double; };
 struct F32 { using S = float2; using R = float; };
 struct H16 { using S = uint32_t; using R = float; };   // lo: f, hi: g (IEEE half)
@@ -87,7 +102,7 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 
 // Element i of the population array starting at p; p MUST be the same for
 // every lane of the wave (it is read from the first active lane).  The byte
-// offset is formed in 32 bits (the library keeps every population array
+// offset is formed in 32 bits (the library keeps every population row
 // below 4 GiB).
 template <typename T>
 __device__ __forceinline__ const T& at32(const T* p, uint32_t i) {
@@ -98,90 +113,129 @@ __device__ __forceinline__ T& at32(T* p, uint32_t i) {
   return *(T*)((char*)uniform_ptr(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
 }
 
-template <typename C> struct Codec;
-// p is the (wave-uniform) base of direction l's pair array, i a 32-bit node
-// offset.
-template <> struct Codec<F64> {
-  static __device__ __forceinline__ void ld(const double2* p, uint32_t i, double& f, double& g,
-                                            double, double) {
-    const double2 v = at32(p, i);
-    f = v.x;
-    g = v.y;
-  }
-  static __device__ __forceinline__ void st(double2* p, uint32_t i, double f, double g, double,
-                                            double) {
-    at32(p, i) = make_double2(f, g);
-  }
-};
-template <> struct Codec<F32> {
-  static __device__ __forceinline__ void ld(const float2* p, uint32_t i, float& f, float& g, float,
-                                            float) {
-    const float2 v = at32(p, i);
-    f = v.x;
-    g = v.y;
-  }
-  static __device__ __forceinline__ void st(float2* p, uint32_t i, float f, float g, float, float) {
-    at32(p, i) = make_float2(f, g);
-  }
-};
-template <> struct Codec<H16> {
-  static __device__ __forceinline__ void ld(const uint32_t* p, uint32_t i, float& f, float& g,
-                                            float fr, float gr) {
-    const uint32_t u = at32(p, i);
-    f = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu)) + fr;
-    g = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16)) + gr;
-  }
-  static __device__ __forceinline__ void st(uint32_t* p, uint32_t i, float f, float g, float fr,
-                                            float gr) {
-    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)(f - fr));
-    const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)(g - gr));
-    at32(p, i) = lo | (hi << 16);
-  }
-};
 __device__ __forceinline__ uint32_t bf16_rne(float v) {
   uint32_t u = __builtin_bit_cast(uint32_t, v);
   u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
   return u >> 16;
 }
-template <> struct Codec<B16> {
-  static __device__ __forceinline__ void ld(const uint32_t* p, uint32_t i, float& f, float& g,
-                                            float fr, float gr) {
-    const uint32_t u = at32(p, i);
-    f = __builtin_bit_cast(float, u << 16) + fr;
-    g = __builtin_bit_cast(float, u & 0xFFFF0000u) + gr;
-  }
-  static __device__ __forceinline__ void st(uint32_t* p, uint32_t i, float f, float g, float fr,
-                                            float gr) {
-    at32(p, i) = bf16_rne(f - fr) | (bf16_rne(g - gr) << 16);
-  }
-};
 
-// Stored word -> (f, g) without touching memory (the word was loaded before).
-template <typename C> struct Unpack;
-template <> struct Unpack<F64> {
-  static __device__ __forceinline__ void run(double2 w, double& f, double& g, double, double) {
+// Per storage form: enc/dec of one moving pair word, the row of direction
+// l >= 1, and the rest pair (type T0).  kResidual: stores keep the rounding
+// residuals and the rest pair is updated in the remainder form.
+template <typename C> struct Codec;
+template <> struct Codec<F64> {
+  using S = double2;
+  using R = double;
+  using T0 = double;
+  static constexpr bool kResidual = false;
+  static __device__ __forceinline__ void dec(S w, R& f, R& g, R, R) { f = w.x; g = w.y; }
+  static __device__ __forceinline__ S enc(R f, R g, R, R) { return make_double2(f, g); }
+  static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) { return b + (size_t)l * N; }
+  static __device__ __forceinline__ S* row(S* b, int l, size_t N) { return b + (size_t)l * N; }
+  static __device__ __forceinline__ void ld0(const S* b, uint32_t i, T0& f, T0& g) {
+    const S w = at32(b, i);
     f = w.x;
     g = w.y;
   }
+  static __device__ __forceinline__ void st0(S* b, uint32_t i, T0 f, T0 g) { at32(b, i) = make_double2(f, g); }
 };
-template <> struct Unpack<F32> {
-  static __device__ __forceinline__ void run(float2 w, float& f, float& g, float, float) {
+template <> struct Codec<F32> {
+  using S = float2;
+  using R = float;
+  using T0 = float;
+  static constexpr bool kResidual = false;
+  static __device__ __forceinline__ void dec(S w, R& f, R& g, R, R) { f = w.x; g = w.y; }
+  static __device__ __forceinline__ S enc(R f, R g, R, R) { return make_float2(f, g); }
+  static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) { return b + (size_t)l * N; }
+  static __device__ __forceinline__ S* row(S* b, int l, size_t N) { return b + (size_t)l * N; }
+  static __device__ __forceinline__ void ld0(const S* b, uint32_t i, T0& f, T0& g) {
+    const S w = at32(b, i);
     f = w.x;
     g = w.y;
   }
+  static __device__ __forceinline__ void st0(S* b, uint32_t i, T0 f, T0 g) { at32(b, i) = make_float2(f, g); }
 };
-template <> struct Unpack<H16> {
-  static __device__ __forceinline__ void run(uint32_t u, float& f, float& g, float fr, float gr) {
+// The two 16-bit forms share the layout and differ in enc/dec only.
+struct Dev16 {
+  using S = uint32_t;
+  using R = float;
+  using T0 = double;
+  static constexpr bool kResidual = true;
+  static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) {
+    return b + (size_t)(l + 3) * N;
+  }
+  static __device__ __forceinline__ S* row(S* b, int l, size_t N) { return b + (size_t)(l + 3) * N; }
+  static __device__ __forceinline__ void ld0(const S* b, uint32_t i, T0& f, T0& g) {
+    const double2 w = at32((const double2*)b, i);
+    f = w.x;
+    g = w.y;
+  }
+  static __device__ __forceinline__ void st0(S* b, uint32_t i, T0 f, T0 g) {
+    at32((double2*)b, i) = make_double2(f, g);
+  }
+};
+template <> struct Codec<H16> : Dev16 {
+  static __device__ __forceinline__ void dec(uint32_t u, float& f, float& g, float fr, float gr) {
     f = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu)) + fr;
     g = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16)) + gr;
   }
+  static __device__ __forceinline__ uint32_t enc(float f, float g, float fr, float gr) {
+    const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)(f - fr));
+    const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)(g - gr));
+    return lo | (hi << 16);
+  }
+  // enc, adding (value - decoded value) to rf, rg: the decode's own FP32
+  // rounding is included, and the difference of the two close floats is
+  // exact, so the rest pair receives what the decoder will miss
+  static __device__ __forceinline__ uint32_t enc_res(float f, float g, float fr, float gr, float& rf,
+                                                     float& rg) {
+    const _Float16 hf = (_Float16)(f - fr), hg = (_Float16)(g - gr);
+    rf += f - ((float)hf + fr);
+    rg += g - ((float)hg + gr);
+    return (uint32_t)__builtin_bit_cast(uint16_t, hf) | ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
+  }
 };
-template <> struct Unpack<B16> {
-  static __device__ __forceinline__ void run(uint32_t u, float& f, float& g, float fr, float gr) {
+template <> struct Codec<B16> : Dev16 {
+  static __device__ __forceinline__ void dec(uint32_t u, float& f, float& g, float fr, float gr) {
     f = __builtin_bit_cast(float, u << 16) + fr;
     g = __builtin_bit_cast(float, u & 0xFFFF0000u) + gr;
   }
+  static __device__ __forceinline__ uint32_t enc(float f, float g, float fr, float gr) {
+    return bf16_rne(f - fr) | (bf16_rne(g - gr) << 16);
+  }
+  static __device__ __forceinline__ uint32_t enc_res(float f, float g, float fr, float gr, float& rf,
+                                                     float& rg) {
+    const uint32_t uf = bf16_rne(f - fr), ug = bf16_rne(g - gr);
+    rf += f - (__builtin_bit_cast(float, uf << 16) + fr);
+    rg += g - (__builtin_bit_cast(float, ug << 16) + gr);
+    return uf | (ug << 16);
+  }
 };
+
+// Load the pair of direction l (any l) of node i, in the compute type.
+template <typename C, typename R = typename C::R>
+__device__ __forceinline__ void load_pair(const typename C::S* b, int l, size_t N, uint32_t i, R& f,
+                                          R& g, R fr, R gr) {
+  if (l == 0) {
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(b, i, f0, g0);
+    f = (R)f0;
+    g = (R)g0;
+  } else {
+    Codec<C>::dec(at32(Codec<C>::row(b, l, N), i), f, g, fr, gr);
+  }
+}
+
+// Store the pair of a moving direction l >= 1 of node i; with kResidual the
+// rounding residuals (value - stored value) are added to rf, rg.
+template <typename C, typename R = typename C::R>
+__device__ __forceinline__ void store_moving(typename C::S* b, int l, size_t N, uint32_t i, R f, R g,
+                                             R fr, R gr, R& rf, R& rg) {
+  if constexpr (Codec<C>::kResidual)
+    at32(Codec<C>::row(b, l, N), i) = Codec<C>::enc_res(f, g, fr, gr, rf, rg);
+  else
+    at32(Codec<C>::row(b, l, N), i) = Codec<C>::enc(f, g, fr, gr);
+}
 
 // ----------------------------------------------------------- node arithmetic
 
@@ -219,10 +273,18 @@ __device__ __forceinline__ void moments(const R* f, const R* g, R& rho, R& E) {
   E = e;
 }
 
-// Node-local macroscopic quantities from the node's populations and the
-// three neighbour gradients (psi, E, rho).
+// Momentum sum_l c_l f_l of a node's populations.
 template <typename R>
-__device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R E, R psi,
+__device__ __forceinline__ void momentum(const R* f, R& jx, R& jy, R& jz) {
+  jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
+  jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
+  jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+}
+
+// Node-local macroscopic quantities from the node's moments (rho, E,
+// momentum j) and the three neighbour gradients (psi, E, rho).
+template <typename R>
+__device__ __forceinline__ Macro<R> node_macro(R jx, R jy, R jz, R rho, R E, R psi,
                                                R gpx, R gpy, R gpz, R gEx, R gEy, R gEz,
                                                R grx, R gry, R grz, const DevParams<R>& P) {
   Macro<R> m;
@@ -230,9 +292,9 @@ __device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R 
   m.E = E;
   m.psi = psi;
   m.T = E / rho;
-  m.jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
-  m.jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
-  m.jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+  m.jx = jx;
+  m.jy = jy;
+  m.jz = jz;
   const R gp = -P.G * psi;
   m.Fx = gp * gpx - (gEx - P.T_lat * grx);
   m.Fy = gp * gpy - (gEy - P.T_lat * gry);
@@ -245,9 +307,19 @@ __device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R 
   return m;
 }
 
+template <typename R>
+__device__ __forceinline__ Macro<R> node_macro(const R* f, const R* g, R rho, R E, R psi,
+                                               R gpx, R gpy, R gpz, R gEx, R gEy, R gEz,
+                                               R grx, R gry, R grz, const DevParams<R>& P) {
+  R jx, jy, jz;
+  momentum<R>(f, jx, jy, jz);
+  return node_macro<R>(jx, jy, jz, rho, E, psi, gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
+}
+
 // BGK collision of both populations at one node (eqs. (LBEQ)/(LBEQ2) right
-// hand sides plus the counter-term); emit(l, f*_l, g*_l) receives the
-// post-collision values.
+// hand sides plus the counter-term).  emit(l, f*_l, g*_l, df_l, dg_l)
+// receives the collided values of the moving directions and what the
+// collision took from them; emit.rest(f*_0, g*_0, S) the rest pair, last.
 template <typename R, typename Emit>
 __device__ __forceinline__ void collide(const R* f, const R* g, const Macro<R>& m,
                                         const DevParams<R>& P, Emit&& emit) {
@@ -261,24 +333,31 @@ __device__ __forceinline__ void collide(const R* f, const R* g, const Macro<R>& 
   const R rk = (P.rho_kappa - m.rho) * m.T;
   const R rt = m.rho * (P.T_lat - R(1) / R(3));
 #pragma unroll
-  for (int l = 0; l < Q; ++l) {
+  for (int q = 1; q <= Q; ++q) {
+    const int l = q == Q ? 0 : q;
     const R cu = R(CX[l]) * ux + R(CY[l]) * uy + R(CZ[l]) * uz;
     const R cv = R(CX[l]) * m.vx + R(CY[l]) * m.vy + R(CZ[l]) * m.vz;
     const R w = wlat<R>(l);
     const R feq = w * m.rho * (uu + cu * (R(3) + R(4.5) * cu)) + af<R>(l) * rt;
     const R geq = w * (m.E + gE * (vv + cv * (R(3) + R(4.5) * cv))) + bg<R>(l) * rk;
-    const R fs = f[l] - P.omega_f * (f[l] - feq);
-    const R gs = g[l] - P.omega_g * (g[l] - geq) + w * m.S;
-    emit(l, fs, gs);
+    // what the pair gives up in the collision, and the collided values
+    const R df = P.omega_f * (f[l] - feq);
+    const R dg = P.omega_g * (g[l] - geq) - w * m.S;
+    const R fs = f[l] - df;
+    const R gs = g[l] - dg;
+    if (l == 0)
+      emit.rest(fs, gs, m.S);
+    else
+      emit(l, fs, gs, df, dg);
   }
 }
 
 // Local equilibrium at rest (initial state).
 template <typename R>
-__device__ __forceinline__ void rest_equilibrium(R rho, R T, const DevParams<R>& P, R* f, R* g) {
+__device__ __forceinline__ void rest_equilibrium(R rho, R T, R rho_kappa, R T_lat, R* f, R* g) {
   const R E = rho * T;
-  const R rk = (P.rho_kappa - rho) * T;
-  const R rt = rho * (P.T_lat - R(1) / R(3));
+  const R rk = (rho_kappa - rho) * T;
+  const R rt = rho * (T_lat - R(1) / R(3));
 #pragma unroll
   for (int l = 0; l < Q; ++l) {
     f[l] = wlat<R>(l) * rho + af<R>(l) * rt;

@@ -46,20 +46,23 @@ def cell_params(n, rho_mean, Ra, storage="fp32", T_c=TC, tau_nu=0.5 + 3 * NU, Pr
         Ra_eff, g = 0.0, 0.0
     p = lbm.Params(n, n, n, storage=lbm.STORAGE[storage], tau_nu=tau_nu, tau_kappa=tau_kappa,
                    G=G, T_d=T_d, T_u=T_u, gravity=g, c_v=c_v, rho_kappa=rho_kappa,
-                   rho_ref=rho_mean, T_ref=Tm, periodic_z=periodic_z, **kw)
+                   rho_ref=rho_mean, T_ref=Tm, T_lat=Tm, periodic_z=periodic_z, **kw)
     p.rayleigh = Ra_eff
     return p
 
 
-BOIL_MARGIN = 0.045
+BOIL_MARGIN = 0.12
 
 
 def boiling_density(n, Ra, T_c=TC, margin=BOIL_MARGIN, **kw):
     """Mean density of the boiling cell: `margin` below the mean density of
     the hydrostatic liquid column whose bottom layer sits on the liquid
-    spinodal (the margin equals the zero-gravity gap between 1.93 and the
-    1.975 threshold).  Gravity depends on the density through Ra, so the
-    two are iterated to a fixed point."""
+    spinodal.  Once convection mixes the bulk, the bottom layer of a cell only
+    slightly past that threshold stays liquid (at 128^3, Ra ~ 1e6, margins
+    0.045 and 0.1 formed no vapour within 10^4 steps); at 0.12 and 0.15 a
+    vapour film forms on the bottom wall and breaks up into rising bubbles;
+    from 0.17 on the film persists.  Gravity depends on the density through
+    Ra, so the two are iterated to a fixed point."""
     G = thermo.coupling_for_tc(T_c)
     rho = 1.975 - margin
     for _ in range(20):
@@ -76,12 +79,15 @@ def seeded_density(n, rho_mean, amp, seed):
     return torch.from_numpy(synth.noisy_density(n, n, n, rho_mean, amp, seed)).cuda().reshape(-1)
 
 
-def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None):
-    """Run and record Nu_bot, Nu_top and the bulk-averaged Nu(z) every
-    diag_every steps; returns the record."""
+def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase_every=0):
+    """Run and record Nu_bot, Nu_top, the bulk-averaged Nu(z), the vapour
+    fraction and the density minimum every diag_every steps, and the bubble
+    statistics every phase_every steps (0: only at the end); returns the
+    record."""
     lat = lbm.Lattice(p, rho0)
     tot0 = lat.moments()
-    rec = {"t": [], "nu_bot": [], "nu_top": [], "nu_bulk": [], "mass_drift": [], "ok": True}
+    rec = {"t": [], "nu_bot": [], "nu_top": [], "nu_bulk": [], "mass_drift": [],
+           "vapour_fraction": [], "rho_min": [], "phases_t": [], "ok": True}
     n = p.nz
     bulk = slice(n // 4, 3 * n // 4)
     step_ms = 0.0
@@ -107,9 +113,23 @@ def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None):
         rec["nu_top"].append(nt)
         rec["nu_bulk"].append(float(np.mean(nu_z[bulk])))
         rec["mass_drift"].append(float(tot[0] / tot0[0] - 1))
+        _, fl = lat.fields()
+        rec["vapour_fraction"].append(float((fl[0] < 1.0).double().mean()))
+        rec["rho_min"].append(float(fl[0].min()))
+        del fl
+        if phase_every and t % phase_every == 0:
+            ph = phase_statistics(lat)
+            vols = ph.pop("bubble_volumes")
+            ph.update(t=t, max_volume=max(vols, default=0),
+                      mean_volume=float(np.mean(vols)) if vols else 0.0)
+            rec["phases_t"].append(ph)
+            if log:
+                print(json.dumps({"phases": ph}), file=log, flush=True)
         if log:
             print(json.dumps({"t": t, "nu_bot": round(nb, 4), "nu_top": round(nt, 4),
-                              "nu_bulk": round(rec["nu_bulk"][-1], 4)}), file=log, flush=True)
+                              "nu_bulk": round(rec["nu_bulk"][-1], 4),
+                              "vap": round(rec["vapour_fraction"][-1], 5),
+                              "rho_min": round(rec["rho_min"][-1], 4)}), file=log, flush=True)
     if rec["ok"]:
         nb, nt, nu_z, T_z = lat.nusselt()
         rec["T_z"] = [float(x) for x in T_z]
@@ -200,23 +220,27 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--noise", type=float, default=0.01)
     ap.add_argument("--ckpt", type=int, default=20)
+    ap.add_argument("--margin", type=float, default=BOIL_MARGIN)
+    ap.add_argument("--phase-every", type=int, default=0,
+                    help="steps between bubble statistics (0: only at the end)")
+    ap.add_argument("--tc", type=float, default=TC)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     lbm.load_library()
     res = {}
     log = sys.stderr
     if a.rho is None:
-        a.rho = boiling_density(a.n, a.ra)
+        a.rho = boiling_density(a.n, a.ra, T_c=a.tc, margin=a.margin)
     if a.what == "convection":
-        p = cell_params(a.n, a.rho, a.ra, a.storage)
-        rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log)
+        p = cell_params(a.n, a.rho, a.ra, a.storage, T_c=a.tc)
+        rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
         res = _summary(rec, p)
         if rec["ok"]:
             res["phases"] = phase_statistics(rec["lattice"])
     elif a.what == "pair":
         for name, rho in (("boiling", a.rho), ("single_phase", a.rho_single)):
-            p = cell_params(a.n, rho, a.ra, a.storage)
-            rec = convection(p, seeded_density(a.n, rho, a.noise, a.seed), a.steps, a.diag, log)
+            p = cell_params(a.n, rho, a.ra, a.storage, T_c=a.tc)
+            rec = convection(p, seeded_density(a.n, rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
             res[name] = _summary(rec, p)
             if rec["ok"]:
                 res[name]["phases"] = phase_statistics(rec["lattice"])
@@ -224,8 +248,8 @@ def main(argv=None):
             torch.cuda.empty_cache()
     elif a.what == "precision":
         for st in ("fp32", "fp16dev", "bf16dev"):
-            p = cell_params(a.n, a.rho, a.ra, st)
-            rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log)
+            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc)
+            rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
             res[st] = _summary(rec, p)
             if rec["ok"]:
                 res[st]["phases"] = phase_statistics(rec["lattice"])
@@ -244,7 +268,7 @@ def main(argv=None):
         out = {}
         d = torch.from_numpy(synth.random_unit_field(a.n, a.n, a.n, 7)).cuda().reshape(-1)
         for st in ("fp32", "fp64"):
-            p = cell_params(a.n, a.rho, a.ra, st)
+            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc)
             rho0 = seeded_density(a.n, a.rho, a.noise, a.seed)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -256,7 +280,7 @@ def main(argv=None):
         for k in ("dJ_dTd", "dJ_dG", "dJ_drho0_dir"):
             out[f"fp32_vs_fp64_rel_{k}"] = abs(out["fp32"][k] / out["fp64"][k] - 1)
         # central differences of the FP64 forward, initial T profile held fixed
-        p = cell_params(a.n, a.rho, a.ra, "fp64")
+        p = cell_params(a.n, a.rho, a.ra, "fp64", T_c=a.tc)
         rho0 = seeded_density(a.n, a.rho, a.noise, a.seed)
         T0 = adjoint.conduction_profile(p)
 

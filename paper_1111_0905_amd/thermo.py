@@ -74,7 +74,7 @@ def gravity_for_rayleigh(Ra: float, L: int, rho: float, T_d: float, T_u: float, 
 def liquid_spinodal(T: float, G: float) -> float:
     """Density above 1 where (dP/drho)_T = 0 (the metastable liquid's end)."""
     lo, hi = 1.0, 50.0
-    for _ in range(200):
+    for _ in range(64):
         mid = 0.5 * (lo + hi)
         if dp_drho(mid, T, G) < 0:
             lo = mid
@@ -83,16 +83,16 @@ def liquid_spinodal(T: float, G: float) -> float:
     return 0.5 * (lo + hi)
 
 
-def liquid_density(P: float, T: float, G: float) -> float:
+def liquid_density(P: float, T: float, G: float, spinodal: float = None) -> float:
     """rho on the liquid branch with P(rho, T) = P; nan when P is below the
     spinodal pressure (no liquid state exists)."""
-    lo = liquid_spinodal(T, G)
+    lo = liquid_spinodal(T, G) if spinodal is None else spinodal
     if pressure(lo, T, G) > P:
         return float("nan")
     hi = lo + 1.0
     while pressure(hi, T, G) < P:
         hi *= 2.0
-    for _ in range(200):
+    for _ in range(64):
         mid = 0.5 * (lo + hi)
         if pressure(mid, T, G) < P:
             lo = mid
@@ -110,9 +110,9 @@ def liquid_column(P_bottom: float, n: int, T_d: float, T_u: float, G: float, g: 
     rho = [liquid_density(P, T[0], G)]
     for k in range(1, n):
         r = rho[-1]
+        sp = liquid_spinodal(T[k], G)
         for _ in range(4):
-            nxt = liquid_density(P - 0.5 * g * (rho[-1] + r), T[k], G)
-            r = nxt
+            r = liquid_density(P - 0.5 * g * (rho[-1] + r), T[k], G, sp)
         P -= 0.5 * g * (rho[-1] + r)
         rho.append(r)
     return rho

@@ -59,3 +59,26 @@ def random_unit_field(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
     u = uniform01(seed, nx * ny * nz) * 2.0 - 1.0
     u /= np.linalg.norm(u)
     return u.reshape(nz, ny, nx)
+
+
+def bubbly_density(n: int, rho_g: float, rho_l: float, n_bubbles: int, r_min: float,
+                   r_max: float, seed: int, width: float = 2.0) -> np.ndarray:
+    """A periodic n^3 liquid of density rho_l holding n_bubbles spherical
+    bubbles of density rho_g: centres uniform in the box, radii uniform in
+    [r_min, r_max], each a tanh profile of the given width (minimum-image
+    distance); where bubbles overlap the lower density wins.  Shape (n, n, n),
+    float64."""
+    u = uniform01(seed, 4 * n_bubbles).reshape(n_bubbles, 4)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    out = np.full((n, n, n), rho_l, dtype=np.float64)
+    for cx, cy, cz, ur in u:
+        c = np.array([cx, cy, cz]) * n
+        R = r_min + (r_max - r_min) * ur
+        d2 = np.zeros_like(out)
+        for a, ca in ((x, c[0]), (y, c[1]), (z, c[2])):
+            da = np.abs(a + 0.5 - ca)
+            da = np.minimum(da, n - da)
+            d2 += da * da
+        prof = rho_g + (rho_l - rho_g) * 0.5 * (1.0 + np.tanh((np.sqrt(d2) - R) / width))
+        out = np.minimum(out, prof)
+    return out

@@ -42,11 +42,14 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("periodic", [0, 1])
 @pytest.mark.parametrize("shape", [(6, 5, 7), (9, 4, 2)])
-def test_one_step_adjoint_matches_oracle_vjp(glbm, periodic, shape):
+def test_one_step_adjoint_matches_oracle_vjp(glbm, periodic, shape, storage):
+    # the adjoint arithmetic is FP64 for every storage form, so an FP32 handle
+    # linearises about the given FP64 state exactly as an FP64 handle does
     nx, ny, nz = shape
-    print(f"case: one-step adjoint {shape} periodic={periodic}", flush=True)
+    print(f"case: one-step adjoint {shape} periodic={periodic} {storage}", flush=True)
     kw = _kw()
     p_o = olbm.Params(nx, ny, nz, periodic_z=bool(periodic), **kw)
     rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 21)
@@ -63,7 +66,8 @@ def test_one_step_adjoint_matches_oracle_vjp(glbm, periodic, shape):
     out = torch.cat([fo, go])
     ds, dG, dTd = torch.autograd.grad(out, [s_r, Gt, Tdt], grad_outputs=lam, allow_unused=True)
     # GPU adjoint
-    p_g = glbm.Params(nx, ny, nz, storage=glbm.LBM_FP64, periodic_z=periodic, adjoint=1, **kw)
+    p_g = glbm.Params(nx, ny, nz, storage=glbm.STORAGE[storage], periodic_z=periodic, adjoint=1,
+                      **kw)
     lat = glbm.Lattice(p_g, torch.from_numpy(rho0).cuda())
     st = s.cuda().contiguous()
     lam_g = lam.cuda().contiguous()
@@ -134,7 +138,8 @@ def test_gradients_match_central_differences(glbm):
     n = 12
     n_steps = 10
     print("case: 12^3 FD check, 10 steps", flush=True)
-    kw = _kw(tau_nu=1.0, tau_kappa=1.0, gravity=1e-5)
+    # T_lat held at its value for the unperturbed T_d (the gradient's convention)
+    kw = _kw(tau_nu=1.0, tau_kappa=1.0, gravity=1e-5, T_lat=0.9 * TC)
     rho0 = torch.from_numpy(synth.noisy_density(n, n, n, 1.18, 0.01, 99)).cuda().reshape(-1)
     p = glbm.Params(n, n, n, storage=glbm.LBM_FP64, **kw)
     T0 = adjoint.conduction_profile(p)
