@@ -23,7 +23,7 @@ import torch
 
 from . import lbm, thermo
 
-TC = 0.12                          # linear stability margin at tau_nu = 0.5495 ends near 0.16
+TC = 0.08                          # walled-column linear stability ends between 0.08 and 0.1
 NU = 0.0165                       # kinematic viscosity of Table 1
 
 
@@ -31,7 +31,9 @@ def cell_params(n, rho_mean, Ra, storage="fp32", T_c=TC, tau_nu=0.5 + 3 * NU, Pr
                 rho_kappa=0.5, c_v=1.0, periodic_z=0, **kw):
     """Parameters of the convection cell: T_d = 0.95 T_c, T_u = 0.85 T_c,
     tau_kappa from Pr = 9 in the liquid at the mid temperature (Table 1),
-    gravity from the Rayleigh number at mid height."""
+    gravity from the Rayleigh number at mid height.  The adiabatic gradient
+    grows with g, so Ra has a maximum over g; a larger request is capped at
+    0.7 of it (p.rayleigh holds the Ra used)."""
     G = thermo.coupling_for_tc(T_c)
     T_d, T_u = 0.95 * T_c, 0.85 * T_c
     Tm = 0.5 * (T_d + T_u)
@@ -59,10 +61,10 @@ def boiling_density(n, Ra, T_c=TC, margin=BOIL_MARGIN, **kw):
     the hydrostatic liquid column whose bottom layer sits on the liquid
     spinodal.  Once convection mixes the bulk, the bottom layer of a cell only
     slightly past that threshold stays liquid (at 128^3, Ra ~ 1e6, margins
-    0.045 and 0.1 formed no vapour within 10^4 steps); at 0.12 and 0.15 a
-    vapour film forms on the bottom wall and breaks up into rising bubbles;
-    from 0.17 on the film persists.  Gravity depends on the density through
-    Ra, so the two are iterated to a fixed point."""
+    0.045 and 0.1 formed no vapour within 10^4 steps); at 0.12 a vapour film
+    forms on the bottom wall and breaks up into rising bubbles within 3 x 10^4
+    steps; at 0.16 and above the film persists.  Gravity depends on the
+    density through Ra, so the two are iterated to a fixed point."""
     G = thermo.coupling_for_tc(T_c)
     rho = 1.975 - margin
     for _ in range(20):
@@ -74,9 +76,25 @@ def boiling_density(n, Ra, T_c=TC, margin=BOIL_MARGIN, **kw):
     return rho
 
 
-def seeded_density(n, rho_mean, amp, seed):
+def seeded_density(n, rho_mean, amp, seed, profile=None):
+    """rho_mean (1 + amp (2u - 1)) per node, u seeded uniform; with a
+    vertical profile rho(z) of mean rho_mean the field is scaled plane by
+    plane to it (the same noise either way)."""
     import synth
-    return torch.from_numpy(synth.noisy_density(n, n, n, rho_mean, amp, seed)).cuda().reshape(-1)
+    r = synth.noisy_density(n, n, n, rho_mean, amp, seed)
+    if profile is not None:
+        r *= (np.asarray(profile) / rho_mean).reshape(n, 1, 1)
+    return torch.from_numpy(r).cuda().reshape(-1)
+
+
+def initial_density(p, n, rho_mean, amp, seed):
+    """Seeded field on the hydrostatic liquid column when one exists (a
+    uniform start would launch a pressure wave of amplitude g rho L, which
+    the weakly damped liquid at tau_nu = 0.5495 does not survive at
+    rho = 2.49); uniform mean density otherwise (the boiling cell, whose
+    bottom layer has no liquid state)."""
+    prof = thermo.hydrostatic_profile(n, rho_mean, p.T_d, p.T_u, p.G, p.gravity)
+    return seeded_density(n, rho_mean, amp, seed, prof), prof is not None
 
 
 def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase_every=0):
@@ -233,8 +251,10 @@ def main(argv=None):
         a.rho = boiling_density(a.n, a.ra, T_c=a.tc, margin=a.margin)
     if a.what == "convection":
         p = cell_params(a.n, a.rho, a.ra, a.storage, T_c=a.tc)
-        rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
+        rho0, hydro = initial_density(p, a.n, a.rho, a.noise, a.seed)
+        rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every)
         res = _summary(rec, p)
+        res["hydrostatic_start"] = hydro
         if rec["ok"]:
             res["phases"] = phase_statistics(rec["lattice"])
     elif a.what == "pair":
@@ -306,6 +326,8 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write(js)
     print(js[:2000])
+    if res.get("ok") is False:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -126,3 +126,27 @@ def boiling_threshold_density(n: int, T_d: float, T_u: float, G: float, g: float
     rs = liquid_spinodal(T0, G)
     rho = liquid_column(pressure(rs, T0, G) + 1e-15, n, T_d, T_u, G, g)
     return sum(rho) / n
+
+
+def hydrostatic_profile(n: int, rho_mean: float, T_d: float, T_u: float, G: float, g: float):
+    """Liquid column of mean density rho_mean in hydrostatic balance on the
+    conduction temperature profile (liquid_column with the bottom pressure
+    found by bisection); None when some plane would have no liquid state."""
+    T0 = T_d + (T_u - T_d) * 0.5 / n
+    lo = pressure(liquid_spinodal(T0, G), T0, G) + 1e-15
+    def mean_at(Pb):
+        r = liquid_column(Pb, n, T_d, T_u, G, g)
+        return sum(r) / n if all(x == x for x in r) else float("nan")
+    m_lo = mean_at(lo)
+    if not (m_lo == m_lo) or m_lo > rho_mean:
+        return None
+    hi = lo + 1.0
+    while mean_at(hi) < rho_mean:
+        hi = lo + 2.0 * (hi - lo)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if mean_at(mid) < rho_mean:
+            lo = mid
+        else:
+            hi = mid
+    return liquid_column(0.5 * (lo + hi), n, T_d, T_u, G, g)

@@ -44,3 +44,34 @@ def test_stable_around_rest_states(taus, state):
     assert max(radii) < 1 + 1e-9
     # the conserved modes sit exactly on the unit circle at k = 0
     assert abs(radii[0] - 1) < 1e-9
+
+
+def _walled_column_radius(Tc, rho, n=24, taus=(0.5495, 0.5947)):
+    """Largest |eigenvalue| of the one-step Jacobian of a 1 x 1 x n column
+    between two isothermal walls, about the uniform rest state."""
+    Tm = 0.9 * Tc
+    p = lbm.Params(1, 1, n, tau_nu=taus[0], tau_kappa=taus[1], G=eos.coupling_for_tc(Tc),
+                   T_lat=Tm, T_d=Tm, T_u=Tm)
+    shape = (n, 1, 1)
+    f, g = lbm.init_state(p, torch.full(shape, rho, dtype=DT), torch.full(shape, Tm, dtype=DT))
+    s0 = torch.cat([f, g]).reshape(-1)
+
+    def fn(s):
+        s = s.view(38, *shape)
+        a, b = lbm.step(p, s[:19], s[19:])
+        return torch.cat([a, b]).reshape(-1)
+
+    J = torch.autograd.functional.jacobian(fn, s0, vectorize=True).numpy()
+    return float(np.abs(np.linalg.eigvals(J)).max())
+
+
+@pytest.mark.parametrize("rho", [1.8, 2.49])
+def test_walled_column_stable_at_convection_cell_tc(rho):
+    # the convection cell runs at T_c = 0.08 with liquid densities up to 2.49
+    assert _walled_column_radius(0.08, rho) < 1 + 1e-9
+
+
+def test_walled_column_unstable_for_hotter_critical_point():
+    # a wall-localised oscillation (about 12 steps per period) grows for the
+    # dense liquid once T_c reaches 0.1, which is why the cell stays at 0.08
+    assert _walled_column_radius(0.1, 2.49) > 1.002
