@@ -185,7 +185,8 @@ def main():
     rho0 = torch.from_numpy(seeded_density(n, rho_mean)).cuda().reshape(-1)
 
     if args.sweep:
-        combos = [(0, 32, 16), (2, 64, 16), (2, 64, 8), (0, 64, 8), (2, 32, 16), (0, 32, 16)]
+        combos = [(0, 32, 16), (0, 64, 8), (0, 64, 4), (0, 64, 2), (0, 32, 8), (2, 64, 16),
+                  (2, 64, 8), (2, 64, 4), (2, 32, 16)]
         for kernel, tx, ty in combos:
             for zc in (0,):
                 r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,

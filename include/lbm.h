@@ -184,6 +184,35 @@ int lbm_moments(lbm_handle* h, double* totals, double* fields);
  */
 int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, double* T_z);
 
+/* node quantities for lbm_histogram */
+enum {
+  LBM_Q_RHO = 0,       /* density */
+  LBM_Q_T = 1,         /* temperature E / rho */
+  LBM_Q_VZ = 2,        /* vertical physical velocity */
+  LBM_Q_HEATFLUX = 3   /* convective heat flux rho U v_z, U = c_v T + (G/4) exp(-2/rho) */
+};
+
+/*
+ * Histogram of node quantities over the planes k0 <= k < k1: the joint
+ * (rho, T) distribution of Fig. 2 (top panel, T-rho scatter against the
+ * equilibrium curves, per region of the cell) and the pdf of the bulk heat
+ * flux rho U u_z of Fig. 2 (inset of the bottom panel), eq. (flux).
+ *   qx, qy: LBM_Q_*; qy = -1 for a 1-D histogram (then ny_bins = 1).
+ *   Uniform bins: a node falls in bin (bx, by) = (floor((x - x_lo) nx_bins /
+ *   (x_hi - x_lo)), likewise y) when 0 <= bx < nx_bins and 0 <= by < ny_bins,
+ *   the scale computed once in FP64 as nx_bins / (x_hi - x_lo); x, y in FP64
+ *   (rho and E summed in FP64 from the stored populations).
+ *   counts: device, nx_bins * ny_bins uint64 (row-major, by fastest),
+ *     overwritten.  out_of_range (host, may be NULL): nodes in no bin.
+ *   sums (host, 5 doubles, may be NULL): [nodes, sum x, sum x^2, sum y, sum y^2]
+ *     over all nodes of the planes, in or out of range (FP64).
+ * Synchronises the stream.  LBM_EINVAL for an empty plane or bin range, an
+ * unknown quantity or more than 2^26 bins.
+ */
+int lbm_histogram(lbm_handle* h, int32_t k0, int32_t k1, int32_t qx, double x_lo, double x_hi,
+                  int32_t nx_bins, int32_t qy, double y_lo, double y_hi, int32_t ny_bins,
+                  uint64_t* counts, uint64_t* out_of_range, double* sums);
+
 /* Copy the current state to / from a canonical FP64 state (device, 38*N
  * doubles, layout above).  set_state encodes to the handle's storage and
  * resets lbm_time to 0.  Both are asynchronous on the stream. */

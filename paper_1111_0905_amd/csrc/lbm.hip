@@ -521,6 +521,96 @@ __global__ __launch_bounds__(256) void k_diag(const typename C::S* __restrict__ 
   }
 }
 
+// Histogram of node quantities over planes [k0, k1) (joint histogram of two
+// quantities, or of one when qy < 0), plus FP64 block partial sums
+// [count, sum x, sum x^2, sum y, sum y^2, out of range].  A node falls in bin
+// (floor((x - xlo) * xscale), floor((y - ylo) * yscale)) when both lie in
+// [0, nbins); x, y in FP64 from the FP64 node sums.  Bins are counted in LDS
+// (nbins <= kLdsBins) or straight into `counts`.
+struct HistSpec {
+  int k0, k1, qx, qy, nxb, nyb;
+  double xlo, xscale, ylo, yscale;
+};
+constexpr int kLdsBins = 16384;
+
+template <typename C, typename R = typename C::R>
+__global__ __launch_bounds__(256) void k_hist(const typename C::S* __restrict__ in,
+                                              const R* __restrict__ srho, const R* __restrict__ sE,
+                                              DevParams<R> P, double c_v, double G, HistSpec hs,
+                                              unsigned long long* __restrict__ counts,
+                                              double* __restrict__ partials) {
+  extern __shared__ uint32_t sh_bins[];
+  __shared__ double sh[4];
+  const int nbins = hs.nxb * hs.nyb;
+  const bool lds = nbins <= kLdsBins;
+  if (lds)
+    for (int q = threadIdx.x; q < nbins; q += blockDim.x) sh_bins[q] = 0u;
+  __syncthreads();
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t A = (size_t)P.nx * P.ny;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (size_t n = (size_t)hs.k0 * A + blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+       n < (size_t)hs.k1 * A; n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / A);
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(in, (uint32_t)n, f0, g0);
+    double rho = (double)f0, E = (double)g0;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      rho += (double)f[l];
+      E += (double)g[l];
+    }
+    const double T = E / rho;
+    const double vz = (double)m.vz;
+    auto pick = [&](int q) {
+      switch (q) {
+        case LBM_Q_RHO: return rho;
+        case LBM_Q_T: return T;
+        case LBM_Q_VZ: return vz;
+        default: return rho * (c_v * T + 0.25 * G * exp(-2.0 / rho)) * vz;   // rho U v_z
+      }
+    };
+    const double x = pick(hs.qx);
+    const double y = hs.qy >= 0 ? pick(hs.qy) : 0.0;
+    acc[0] += 1.0;
+    acc[1] += x;
+    acc[2] += x * x;
+    acc[3] += y;
+    acc[4] += y * y;
+    const double fx = (x - hs.xlo) * hs.xscale;
+    const double fy = hs.qy >= 0 ? (y - hs.ylo) * hs.yscale : 0.0;
+    if (fx >= 0.0 && fx < (double)hs.nxb && fy >= 0.0 && fy < (double)hs.nyb) {
+      const int b = (int)fx * hs.nyb + (int)fy;
+      if (lds)
+        atomicAdd(&sh_bins[b], 1u);
+      else
+        atomicAdd(&counts[b], 1ull);
+    } else {
+      acc[5] += 1.0;
+    }
+  }
+  __syncthreads();
+  if (lds)
+    for (int q = threadIdx.x; q < nbins; q += blockDim.x)
+      if (sh_bins[q]) atomicAdd(&counts[q], (unsigned long long)sh_bins[q]);
+  for (int q = 0; q < 6; ++q) {
+    const double sum = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * 8 + q] = sum;
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, size_t n) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    p[q] = 0ull;
+}
+
 // Fixed-order sum of the block partials (deterministic).
 __global__ __launch_bounds__(256) void k_finish_totals(const double* __restrict__ partials,
                                                        int nblk, double* __restrict__ out) {
@@ -1153,6 +1243,34 @@ int do_nusselt(lbm_handle* h, double* nb, double* nt, double* nu_z, double* T_z)
   return LBM_OK;
 }
 
+template <typename C>
+int do_hist(lbm_handle* h, const HistSpec& hs, unsigned long long* counts, double* sums,
+            uint64_t* out_of_range) {
+  using R = typename C::R;
+  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  if (rc) return rc;
+  const DevParams<R> P = dev_params<R>(h->p);
+  const size_t nbins = (size_t)hs.nxb * hs.nyb;
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(nbins, 256)), dim3(256), 0, h->stream, counts, nbins);
+  HIP_TRY(hipGetLastError());
+  const size_t nodes = (size_t)(hs.k1 - hs.k0) * h->p.nx * h->p.ny;
+  const int nblk = std::max(1, std::min(kDiagBlocks, grid_for(nodes, 256)));
+  const size_t lds = nbins <= (size_t)kLdsBins ? nbins * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL((k_hist<C>), dim3(nblk), dim3(256), lds, h->stream,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
+                     h->p.c_v, h->p.G, hs, counts, h->partials);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
+  HIP_TRY(hipGetLastError());
+  double out[7];
+  HIP_TRY(hipMemcpyAsync(out, h->small, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (sums)
+    for (int q = 0; q < 5; ++q) sums[q] = out[q];
+  if (out_of_range) *out_of_range = (uint64_t)out[5];
+  return LBM_OK;
+}
+
 template <typename R>
 int do_adjoint_step(lbm_handle* h, const double* st, const double* lam1, double* lam0,
                     double* grads) {
@@ -1228,6 +1346,11 @@ template <typename C> struct SetFn {
 };
 template <typename C> struct MomFn {
   static int run(lbm_handle* h, double* t, double* f) { return do_moments<C>(h, t, f); }
+};
+template <typename C> struct HistFn {
+  static int run(lbm_handle* h, HistSpec hs, unsigned long long* c, double* s, uint64_t* o) {
+    return do_hist<C>(h, hs, c, s, o);
+  }
 };
 template <typename C> struct NuFn {
   static int run(lbm_handle* h, double* a, double* b, double* c, double* d) {
@@ -1348,6 +1471,31 @@ int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, dou
   if (h->p.periodic_z) return fail(LBM_EINVAL, "Nusselt numbers need walls");
   if (!(h->p.T_d != h->p.T_u)) return fail(LBM_EINVAL, "Nusselt numbers need T_d != T_u");
   return dispatch<NuFn>(h->p.storage, h, nu_bot, nu_top, nu_z, T_z);
+}
+
+int lbm_histogram(lbm_handle* h, int32_t k0, int32_t k1, int32_t qx, double x_lo, double x_hi,
+                  int32_t nx_bins, int32_t qy, double y_lo, double y_hi, int32_t ny_bins,
+                  uint64_t* counts, uint64_t* out_of_range, double* sums) {
+  if (!h || !counts) return fail(LBM_EINVAL, "NULL argument");
+  if (k0 < 0 || k1 > h->p.nz || k0 >= k1) return fail(LBM_EINVAL, "need 0 <= k0 < k1 <= nz");
+  if (qx < LBM_Q_RHO || qx > LBM_Q_HEATFLUX || qy < -1 || qy > LBM_Q_HEATFLUX)
+    return fail(LBM_EINVAL, "unknown quantity");
+  if (nx_bins < 1 || ny_bins < 1 || (qy < 0 && ny_bins != 1))
+    return fail(LBM_EINVAL, "bins must be >= 1 (ny_bins = 1 for a 1-D histogram)");
+  if ((double)nx_bins * (double)ny_bins > 67108864.0) return fail(LBM_EINVAL, "too many bins");
+  if (!(x_hi > x_lo) || (qy >= 0 && !(y_hi > y_lo))) return fail(LBM_EINVAL, "empty bin range");
+  HistSpec hs;
+  hs.k0 = k0;
+  hs.k1 = k1;
+  hs.qx = qx;
+  hs.qy = qy;
+  hs.nxb = nx_bins;
+  hs.nyb = ny_bins;
+  hs.xlo = x_lo;
+  hs.xscale = (double)nx_bins / (x_hi - x_lo);
+  hs.ylo = qy >= 0 ? y_lo : 0.0;
+  hs.yscale = qy >= 0 ? (double)ny_bins / (y_hi - y_lo) : 1.0;
+  return dispatch<HistFn>(h->p.storage, h, hs, (unsigned long long*)counts, sums, out_of_range);
 }
 
 int lbm_get_state(lbm_handle* h, double* state) {

@@ -97,17 +97,26 @@ def initial_density(p, n, rho_mean, amp, seed):
     return seeded_density(n, rho_mean, amp, seed, prof), prof is not None
 
 
+FLUX_RANGE = 400.0      # heat-flux pdf range, +- in units of the diffusive flux kappa dT / L
+FLUX_BINS = 800
+
+
 def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase_every=0):
     """Run and record Nu_bot, Nu_top, the bulk-averaged Nu(z), the vapour
     fraction and the density minimum every diag_every steps, and the bubble
-    statistics every phase_every steps (0: only at the end); returns the
-    record."""
+    statistics every phase_every steps (0: only at the end).  Over the second
+    half of the run the bulk heat flux rho U v_z is histogrammed at every
+    record (the pdf of Fig. 2, bottom inset).  Returns the record."""
     lat = lbm.Lattice(p, rho0)
     tot0 = lat.moments()
     rec = {"t": [], "nu_bot": [], "nu_top": [], "nu_bulk": [], "mass_drift": [],
            "vapour_fraction": [], "rho_min": [], "phases_t": [], "ok": True}
     n = p.nz
     bulk = slice(n // 4, 3 * n // 4)
+    q_unit = thermo.kappa(p.tau_kappa, p.rho_kappa, p.c_v) * (p.T_d - p.T_u) / n
+    flux_counts = np.zeros(FLUX_BINS, dtype=np.int64)
+    flux_sums = np.zeros(5)
+    flux_oor = 0
     step_ms = 0.0
     t = 0
     while t < steps:
@@ -131,6 +140,12 @@ def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase
         rec["nu_top"].append(nt)
         rec["nu_bulk"].append(float(np.mean(nu_z[bulk])))
         rec["mass_drift"].append(float(tot[0] / tot0[0] - 1))
+        if 2 * t > steps:
+            c, o, sm = lat.histogram(n // 4, 3 * n // 4, lbm.LBM_Q_HEATFLUX,
+                                     (-FLUX_RANGE * q_unit, FLUX_RANGE * q_unit), FLUX_BINS)
+            flux_counts += c.cpu().numpy().ravel()
+            flux_oor += o
+            flux_sums += sm
         _, fl = lat.fields()
         rec["vapour_fraction"].append(float((fl[0] < 1.0).double().mean()))
         rec["rho_min"].append(float(fl[0].min()))
@@ -152,10 +167,42 @@ def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase
         nb, nt, nu_z, T_z = lat.nusselt()
         rec["T_z"] = [float(x) for x in T_z]
         rec["nu_z"] = [float(x) for x in nu_z]
+        if flux_sums[0] > 0:
+            mean = flux_sums[1] / flux_sums[0]
+            rec["bulk_flux_pdf"] = {
+                "unit": "kappa (T_d - T_u) / L", "range": [-FLUX_RANGE, FLUX_RANGE],
+                "counts": flux_counts.tolist(), "out_of_range": int(flux_oor),
+                "mean": mean / q_unit,
+                "std": math.sqrt(max(flux_sums[2] / flux_sums[0] - mean * mean, 0.0)) / q_unit,
+                "samples": int(flux_sums[0])}
+        rec["rho_T_hist"] = rho_T_histograms(lat, p)
     rec["ms_per_step"] = step_ms / max(t, 1)
     rec["mlups"] = p.n / (rec["ms_per_step"] * 1e-3) / 1e6
     rec["lattice"] = lat
     return rec
+
+
+def rho_T_histograms(lat, p, rho_bins=150, T_bins=100):
+    """Joint (rho, T) histograms of the bottom (k < L/8), bulk (L/4 <= k <
+    3L/4) and top (k >= 7L/8) regions (Fig. 2, top panel): rho in [0, 3],
+    T in [0.8, 1.0] T_c; counts as nested lists [rho bin][T bin]."""
+    n = p.nz
+    Tc = -p.G / math.e ** 2
+    out = {"rho_range": [0.0, 3.0], "T_range": [0.8 * Tc, 1.0 * Tc]}
+    for name, (k0, k1) in (("bottom", (0, n // 8)), ("bulk", (n // 4, 3 * n // 4)),
+                           ("top", (n - n // 8, n))):
+        c, o, _ = lat.histogram(k0, k1, lbm.LBM_Q_RHO, (0.0, 3.0), rho_bins, lbm.LBM_Q_T,
+                                (0.8 * Tc, 1.0 * Tc), T_bins)
+        out[name] = {"counts": c.cpu().numpy().tolist(), "out_of_range": int(o)}
+    return out
+
+
+def bulk_slope(T_z):
+    """Least-squares slope of the mean temperature over L/4 <= k < 3L/4."""
+    T_z = np.asarray(T_z)
+    n = len(T_z)
+    k = np.arange(n // 4, 3 * n // 4)
+    return float(np.polyfit(k, T_z[k], 1)[0])
 
 
 def profile_asymmetry(T_z, T_d, T_u):
@@ -218,6 +265,11 @@ def _summary(rec, p):
         out["nu_top_mean_2nd_half"] = float(np.mean(rec["nu_top"][half:]))
     if "T_z" in rec:
         out["T_centre_minus_mean_rel"] = profile_asymmetry(rec["T_z"], p.T_d, p.T_u)
+        Tm = 0.5 * (p.T_d + p.T_u)
+        rho = p.rho_ref
+        out["bulk_dTdz"] = bulk_slope(rec["T_z"])
+        out["adiabatic_dTdz"] = -thermo.beta(rho, Tm, p.G) * Tm * p.gravity / thermo.cp(rho, Tm, p.G, p.c_v)
+        out["conductive_dTdz"] = -(p.T_d - p.T_u) / p.nz
     out["params"] = {f: getattr(p, f) for f in ("nx", "ny", "nz", "storage", "tau_nu", "tau_kappa",
                                                  "G", "T_d", "T_u", "gravity", "c_v", "rho_kappa")}
     out["params"]["rayleigh"] = getattr(p, "rayleigh", None)

@@ -17,6 +17,7 @@ import numpy as np
 LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_BF16DEV = 0, 1, 2, 3
 LBM_KERNEL_FUSED, LBM_KERNEL_REFERENCE, LBM_KERNEL_FUSED_RELOAD = 0, 1, 2
 STORAGE = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16dev": LBM_FP16DEV, "bf16dev": LBM_BF16DEV}
+LBM_Q_RHO, LBM_Q_T, LBM_Q_VZ, LBM_Q_HEATFLUX = 0, 1, 2, 3
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblbm.so")
 _lib = None
@@ -101,6 +102,10 @@ def load_library(path: str = _LIB_PATH):
                              ctypes.c_int),
         "lbm_adjoint_init_rho": ([H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
+        "lbm_histogram": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                           ctypes.POINTER(ctypes.c_uint64), D], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -186,6 +191,21 @@ def lbm_nusselt(h: _Handle):
     T_z = (ctypes.c_double * nz)()
     _check(load_library().lbm_nusselt(h.h, ctypes.byref(nb), ctypes.byref(nt), nu_z, T_z))
     return nb.value, nt.value, np.array(nu_z[:]), np.array(T_z[:])
+
+
+def lbm_histogram(h: _Handle, k0: int, k1: int, qx: int, x_range, nx_bins: int, qy: int = -1,
+                  y_range=(0.0, 1.0), ny_bins: int = 1):
+    """(counts [nx_bins, ny_bins] int64 cuda tensor, out_of_range, sums[5]) over planes
+    k0 <= k < k1; sums = [nodes, sum x, sum x^2, sum y, sum y^2]."""
+    import torch
+    counts = torch.empty((nx_bins, ny_bins), dtype=torch.int64, device=h.workspace.device)
+    oor = ctypes.c_uint64()
+    sums = (ctypes.c_double * 5)()
+    _check(load_library().lbm_histogram(h.h, k0, k1, qx, float(x_range[0]), float(x_range[1]),
+                                        nx_bins, qy, float(y_range[0]), float(y_range[1]),
+                                        ny_bins, _dev_ptr(counts, torch.int64, nx_bins * ny_bins),
+                                        ctypes.byref(oor), sums))
+    return counts, oor.value, np.array(sums[:])
 
 
 def lbm_get_state(h: _Handle, out=None):
@@ -279,6 +299,9 @@ class Lattice:
 
     def nusselt(self):
         return lbm_nusselt(self.h)
+
+    def histogram(self, k0, k1, qx, x_range, nx_bins, qy=-1, y_range=(0.0, 1.0), ny_bins=1):
+        return lbm_histogram(self.h, k0, k1, qx, x_range, nx_bins, qy, y_range, ny_bins)
 
     def state(self):
         return lbm_get_state(self.h)
