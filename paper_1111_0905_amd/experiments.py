@@ -87,6 +87,19 @@ def seeded_density(n, rho_mean, amp, seed, profile=None):
     return torch.from_numpy(r).cuda().reshape(-1)
 
 
+def initial_temperature(p, n, amp, seed):
+    """Conduction profile plus seeded noise of amp (T_d - T_u) (2u - 1) per
+    node (seed + 1 so it is independent of the density noise): without a
+    temperature perturbation the convective instability of a quiet liquid
+    grows only from the density noise, over many free-fall times."""
+    import synth
+    k = np.arange(n, dtype=np.float64)
+    Tz = p.T_d + (p.T_u - p.T_d) * (k + 0.5) / n
+    u = synth.noisy_density(n, n, n, 1.0, 1.0, seed + 1) - 1.0
+    T = Tz.reshape(n, 1, 1) + amp * (p.T_d - p.T_u) * u
+    return torch.from_numpy(T).cuda().reshape(-1)
+
+
 def initial_density(p, n, rho_mean, amp, seed):
     """Seeded field on the hydrostatic liquid column when one exists (a
     uniform start would launch a pressure wave of amplitude g rho L, which
@@ -101,13 +114,14 @@ FLUX_RANGE = 400.0      # heat-flux pdf range, +- in units of the diffusive flux
 FLUX_BINS = 800
 
 
-def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase_every=0):
+def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase_every=0,
+               T0=None):
     """Run and record Nu_bot, Nu_top, the bulk-averaged Nu(z), the vapour
     fraction and the density minimum every diag_every steps, and the bubble
     statistics every phase_every steps (0: only at the end).  Over the second
     half of the run the bulk heat flux rho U v_z is histogrammed at every
     record (the pdf of Fig. 2, bottom inset).  Returns the record."""
-    lat = lbm.Lattice(p, rho0)
+    lat = lbm.Lattice(p, rho0, T0)
     tot0 = lat.moments()
     rec = {"t": [], "nu_bot": [], "nu_top": [], "nu_bulk": [], "mass_drift": [],
            "vapour_fraction": [], "rho_min": [], "phases_t": [], "ok": True}
@@ -289,6 +303,8 @@ def main(argv=None):
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--noise", type=float, default=0.01)
+    ap.add_argument("--tnoise", type=float, default=0.05,
+                    help="temperature noise in units of T_d - T_u (0: the plain conduction profile)")
     ap.add_argument("--ckpt", type=int, default=20)
     ap.add_argument("--margin", type=float, default=BOIL_MARGIN)
     ap.add_argument("--phase-every", type=int, default=0,
@@ -304,7 +320,8 @@ def main(argv=None):
     if a.what == "convection":
         p = cell_params(a.n, a.rho, a.ra, a.storage, T_c=a.tc)
         rho0, hydro = initial_density(p, a.n, a.rho, a.noise, a.seed)
-        rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every)
+        T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
+        rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
         res = _summary(rec, p)
         res["hydrostatic_start"] = hydro
         if rec["ok"]:
