@@ -213,6 +213,22 @@ int lbm_histogram(lbm_handle* h, int32_t k0, int32_t k1, int32_t qx, double x_lo
                   int32_t nx_bins, int32_t qy, double y_lo, double y_hi, int32_t ny_bins,
                   uint64_t* counts, uint64_t* out_of_range, double* sums);
 
+/*
+ * Structure functions with horizontal increments (Fig. 3): for r = 1..r_max
+ *   S_2(r) = < (a(x + r e) - a(x))^2 >,  S_4(r) = < (a(x + r e) - a(x))^4 >,
+ * averaged over the nodes of planes k0 <= k < k1 and over e = x and e = y
+ * (periodic), a one of LBM_Q_* (u_z: LBM_Q_VZ; T: LBM_Q_T) in FP64; the
+ * flatness is S_4 / S_2^2.
+ *   work: device, >= lbm_structure_work_bytes(h, k0, k1, r_max) bytes
+ *     (the field over the planes, per-block partial sums), caller-owned.
+ *   out: host, 2 * r_max doubles: [S_2(1..r_max), S_4(1..r_max)].
+ * 1 <= r_max <= 256 and r_max < nx, ny; nx, ny <= 8192.  Deterministic
+ * (fixed-order sums).  Synchronises the stream.
+ */
+size_t lbm_structure_work_bytes(const lbm_handle* h, int32_t k0, int32_t k1, int32_t r_max);
+int lbm_structure_functions(lbm_handle* h, int32_t k0, int32_t k1, int32_t q, int32_t r_max,
+                            double* work, size_t work_bytes, double* out);
+
 /* Copy the current state to / from a canonical FP64 state (device, 38*N
  * doubles, layout above).  set_state encodes to the handle's storage and
  * resets lbm_time to 0.  Both are asynchronous on the stream. */

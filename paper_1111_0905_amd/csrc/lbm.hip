@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "physics.hpp"
@@ -609,6 +610,103 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x)
     p[q] = 0ull;
+}
+
+// Node quantity over planes [k0, k1) into q (FP64, node order within the
+// planes), for the structure functions.
+template <typename C, typename R = typename C::R>
+__global__ __launch_bounds__(256) void k_quantity(const typename C::S* __restrict__ in,
+                                                  const R* __restrict__ srho,
+                                                  const R* __restrict__ sE, DevParams<R> P,
+                                                  double c_v, double G, int k0, int k1, int which,
+                                                  double* __restrict__ q) {
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  const size_t A = (size_t)P.nx * P.ny;
+  for (size_t n = (size_t)k0 * A + blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+       n < (size_t)k1 * A; n += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % P.nx);
+    const int j = (int)((n / P.nx) % P.ny);
+    const int k = (int)(n / A);
+    R f[Q], g[Q];
+    load_node<C>(in, N, (uint32_t)n, P, f, g);
+    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(in, (uint32_t)n, f0, g0);
+    double rho = (double)f0, E = (double)g0;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      rho += (double)f[l];
+      E += (double)g[l];
+    }
+    const double T = E / rho;
+    double v;
+    switch (which) {
+      case LBM_Q_RHO: v = rho; break;
+      case LBM_Q_T: v = T; break;
+      case LBM_Q_VZ: v = (double)m.vz; break;
+      default: v = rho * (c_v * T + 0.25 * G * exp(-2.0 / rho)) * (double)m.vz; break;
+    }
+    q[n - (size_t)k0 * A] = v;
+  }
+}
+
+// Horizontal increments of a field a (planes of nx x ny, `planes` of them):
+// every work-group takes whole lines (along x for line < planes*ny, along y
+// after that) into LDS; thread t handles separation r = t + 1 and sums
+// (a(x + r e) - a(x))^2 and ^4 over the line (periodic).  Per-block partials
+// [block][r][2] go to `part`.
+__global__ __launch_bounds__(256) void k_increments(const double* __restrict__ a, int nx, int ny,
+                                                    int planes, int rmax,
+                                                    double* __restrict__ part) {
+  extern __shared__ double line[];
+  const int t = threadIdx.x;
+  const long long nlx = (long long)planes * ny, nly = (long long)planes * nx;
+  double s2 = 0.0, s4 = 0.0;
+  for (long long L = blockIdx.x; L < nlx + nly; L += gridDim.x) {
+    int len;
+    __syncthreads();
+    if (L < nlx) {  // line along x: plane p, row j
+      len = nx;
+      const double* src = a + (size_t)L * nx;
+      for (int q = t; q < nx; q += blockDim.x) line[q] = src[q];
+    } else {        // line along y: plane p, column i
+      len = ny;
+      const long long c = L - nlx;
+      const int p = (int)(c / nx), i = (int)(c % nx);
+      const double* src = a + (size_t)p * nx * ny + i;
+      for (int q = t; q < ny; q += blockDim.x) line[q] = src[(size_t)q * nx];
+    }
+    __syncthreads();
+    const int r = t + 1;
+    if (r <= rmax && r < len) {
+      for (int q = 0; q < len; ++q) {
+        const int qr = q + r < len ? q + r : q + r - len;
+        const double d = line[qr] - line[q];
+        const double d2 = d * d;
+        s2 += d2;
+        s4 += d2 * d2;
+      }
+    }
+  }
+  if (t < rmax) {
+    part[((size_t)blockIdx.x * rmax + t) * 2] = s2;
+    part[((size_t)blockIdx.x * rmax + t) * 2 + 1] = s4;
+  }
+}
+
+// out[r][2] = sum over blocks of part[block][r][2], fixed order.
+__global__ void k_finish_increments(const double* __restrict__ part, int nblk, int rmax,
+                                    double* __restrict__ out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rmax; r += gridDim.x * blockDim.x) {
+    double s2 = 0.0, s4 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      s2 += part[((size_t)b * rmax + r) * 2];
+      s4 += part[((size_t)b * rmax + r) * 2 + 1];
+    }
+    out[2 * r] = s2;
+    out[2 * r + 1] = s4;
+  }
 }
 
 // Fixed-order sum of the block partials (deterministic).
@@ -1271,6 +1369,42 @@ int do_hist(lbm_handle* h, const HistSpec& hs, unsigned long long* counts, doubl
   return LBM_OK;
 }
 
+constexpr int kIncBlocks = 1024;
+
+template <typename C>
+int do_structure(lbm_handle* h, int k0, int k1, int which, int rmax, double* work, double* out) {
+  using R = typename C::R;
+  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  if (rc) return rc;
+  const DevParams<R> P = dev_params<R>(h->p);
+  const int nx = h->p.nx, ny = h->p.ny, planes = k1 - k0;
+  const size_t nodes = (size_t)planes * nx * ny;
+  hipLaunchKernelGGL((k_quantity<C>), dim3(std::min(kDiagBlocks, grid_for(nodes, 256))), dim3(256),
+                     0, h->stream, (const typename C::S*)h->buf[h->cur], (const R*)h->srho,
+                     (const R*)h->sE, P, h->p.c_v, h->p.G, k0, k1, which, work);
+  HIP_TRY(hipGetLastError());
+  double* part = work + nodes;
+  double* sums = part + (size_t)kIncBlocks * rmax * 2;
+  const size_t lds = (size_t)std::max(nx, ny) * sizeof(double);
+  hipLaunchKernelGGL(k_increments, dim3(kIncBlocks), dim3(256), lds, h->stream, work, nx, ny,
+                     planes, rmax, part);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_increments, dim3(1), dim3(256), 0, h->stream, part, kIncBlocks, rmax,
+                     sums);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> host(2 * (size_t)rmax);
+  HIP_TRY(hipMemcpyAsync(host.data(), sums, sizeof(double) * 2 * rmax, hipMemcpyDeviceToHost,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  // each separation is counted once per node and direction
+  const double cnt = 2.0 * (double)nodes;
+  for (int r = 0; r < rmax; ++r) {
+    out[r] = host[2 * r] / cnt;
+    out[rmax + r] = host[2 * r + 1] / cnt;
+  }
+  return LBM_OK;
+}
+
 template <typename R>
 int do_adjoint_step(lbm_handle* h, const double* st, const double* lam1, double* lam0,
                     double* grads) {
@@ -1350,6 +1484,11 @@ template <typename C> struct MomFn {
 template <typename C> struct HistFn {
   static int run(lbm_handle* h, HistSpec hs, unsigned long long* c, double* s, uint64_t* o) {
     return do_hist<C>(h, hs, c, s, o);
+  }
+};
+template <typename C> struct SfFn {
+  static int run(lbm_handle* h, int k0, int k1, int q, int rmax, double* w, double* o) {
+    return do_structure<C>(h, k0, k1, q, rmax, w, o);
   }
 };
 template <typename C> struct NuFn {
@@ -1496,6 +1635,26 @@ int lbm_histogram(lbm_handle* h, int32_t k0, int32_t k1, int32_t qx, double x_lo
   hs.ylo = qy >= 0 ? y_lo : 0.0;
   hs.yscale = qy >= 0 ? (double)ny_bins / (y_hi - y_lo) : 1.0;
   return dispatch<HistFn>(h->p.storage, h, hs, (unsigned long long*)counts, sums, out_of_range);
+}
+
+size_t lbm_structure_work_bytes(const lbm_handle* h, int32_t k0, int32_t k1, int32_t r_max) {
+  if (!h || k0 < 0 || k1 > h->p.nz || k0 >= k1 || r_max < 1) return 0;
+  return sizeof(double) * ((size_t)(k1 - k0) * h->p.nx * h->p.ny +
+                           (size_t)kIncBlocks * r_max * 2 + 2 * (size_t)r_max);
+}
+
+int lbm_structure_functions(lbm_handle* h, int32_t k0, int32_t k1, int32_t q, int32_t r_max,
+                            double* work, size_t work_bytes, double* out) {
+  if (!h || !work || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (k0 < 0 || k1 > h->p.nz || k0 >= k1) return fail(LBM_EINVAL, "need 0 <= k0 < k1 <= nz");
+  if (q < LBM_Q_RHO || q > LBM_Q_HEATFLUX) return fail(LBM_EINVAL, "unknown quantity");
+  if (r_max < 1 || r_max > 256 || r_max >= h->p.nx || r_max >= h->p.ny)
+    return fail(LBM_EINVAL, "need 1 <= r_max <= 256 and r_max < nx, ny");
+  if ((size_t)std::max(h->p.nx, h->p.ny) * sizeof(double) > 65536)
+    return fail(LBM_EINVAL, "lines longer than 8192 nodes are not supported");
+  if (work_bytes < lbm_structure_work_bytes(h, k0, k1, r_max))
+    return fail(LBM_EWORKSPACE, "work buffer too small (lbm_structure_work_bytes)");
+  return dispatch<SfFn>(h->p.storage, h, (int)k0, (int)k1, (int)q, (int)r_max, work, out);
 }
 
 int lbm_get_state(lbm_handle* h, double* state) {

@@ -190,6 +190,12 @@ def convection(p: lbm.Params, rho0, steps: int, diag_every: int, log=None, phase
                 "std": math.sqrt(max(flux_sums[2] / flux_sums[0] - mean * mean, 0.0)) / q_unit,
                 "samples": int(flux_sums[0])}
         rec["rho_T_hist"] = rho_T_histograms(lat, p)
+        rmax = min(128, p.nx // 2, p.ny // 2)
+        rec["structure"] = {}
+        for name, q in (("vz", lbm.LBM_Q_VZ), ("T", lbm.LBM_Q_T)):
+            s2, s4 = lat.structure_functions(n // 4, 3 * n // 4, q, rmax)
+            rec["structure"][name] = {"S2": s2.tolist(), "S4": s4.tolist(),
+                                      "flatness": (s4 / np.maximum(s2, 1e-300) ** 2).tolist()}
     rec["ms_per_step"] = step_ms / max(t, 1)
     rec["mlups"] = p.n / (rec["ms_per_step"] * 1e-3) / 1e6
     rec["lattice"] = lat

@@ -102,6 +102,11 @@ def load_library(path: str = _LIB_PATH):
                              ctypes.c_int),
         "lbm_adjoint_init_rho": ([H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
+        "lbm_structure_work_bytes": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                                     ctypes.c_size_t),
+        "lbm_structure_functions": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, D],
+                                    ctypes.c_int),
         "lbm_histogram": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                            ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                            ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
@@ -208,6 +213,21 @@ def lbm_histogram(h: _Handle, k0: int, k1: int, qx: int, x_range, nx_bins: int, 
     return counts, oor.value, np.array(sums[:])
 
 
+def lbm_structure_functions(h: _Handle, k0: int, k1: int, q: int, r_max: int):
+    """(S2[r_max], S4[r_max]) for r = 1..r_max, horizontal increments over planes k0..k1-1."""
+    import torch
+    lib = load_library()
+    nbytes = lib.lbm_structure_work_bytes(h.h, k0, k1, r_max)
+    if nbytes == 0:
+        raise LbmError(-1, "invalid planes or r_max")
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=h.workspace.device)
+    out = (ctypes.c_double * (2 * r_max))()
+    _check(lib.lbm_structure_functions(h.h, k0, k1, q, r_max, ctypes.c_void_p(work.data_ptr()),
+                                       nbytes, out))
+    a = np.array(out[:])
+    return a[:r_max], a[r_max:]
+
+
 def lbm_get_state(h: _Handle, out=None):
     """Canonical FP64 state (38, nz, ny, nx) as a cuda tensor."""
     import torch
@@ -302,6 +322,9 @@ class Lattice:
 
     def histogram(self, k0, k1, qx, x_range, nx_bins, qy=-1, y_range=(0.0, 1.0), ny_bins=1):
         return lbm_histogram(self.h, k0, k1, qx, x_range, nx_bins, qy, y_range, ny_bins)
+
+    def structure_functions(self, k0, k1, q, r_max):
+        return lbm_structure_functions(self.h, k0, k1, q, r_max)
 
     def state(self):
         return lbm_get_state(self.h)
