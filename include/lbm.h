@@ -155,6 +155,20 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes,
              const double* rho0, const double* T0, void* stream, lbm_handle** out);
 
+/*
+ * The seeded initial density of the workloads (row a10 of the step's set-up):
+ *   rho0[n] = rho_mean (1 + noise_amp (2 u_n - 1)),  n = i + nx (j + ny k),
+ * u_n = (SplitMix64 output for state seed + (n + 1) 0x9E3779B97F4A7C15) >> 11,
+ * divided by 2^53 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014), in IEEE double without contraction, so the field
+ * is bit-identical to any implementation of the same definition.
+ *   rho0: device, nx*ny*nz doubles, written (caller-owned); stream as lbm_init.
+ * Asynchronous.  LBM_EINVAL for empty sizes, rho_mean <= 0 or noise_amp
+ * outside [0, 1).
+ */
+int lbm_seeded_density(int32_t nx, int32_t ny, int32_t nz, uint64_t seed, double rho_mean,
+                       double noise_amp, double* rho0, void* stream);
+
 /* Advance n >= 0 time steps (asynchronous on the handle's stream). */
 int lbm_step(lbm_handle* h, int64_t n);
 

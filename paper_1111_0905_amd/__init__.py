@@ -8,7 +8,8 @@ providing device memory and the stream.
 from .lbm import (  # noqa: F401
     LBM_BF16DEV, LBM_FP16DEV, LBM_FP32, LBM_FP64, LBM_KERNEL_FUSED, LBM_KERNEL_FUSED_RELOAD,
     LBM_KERNEL_REFERENCE, LbmError, Lattice, Params, lbm_destroy, lbm_get_state, lbm_init,
-    lbm_histogram, lbm_moments, lbm_nusselt, lbm_set_state, lbm_step, lbm_structure_functions,
+    lbm_histogram, lbm_moments, lbm_nusselt, lbm_seeded_density, lbm_set_state, lbm_step,
+    lbm_structure_functions,
     lbm_time, lbm_workspace_bytes,
     load_library,
 )

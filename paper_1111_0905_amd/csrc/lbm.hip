@@ -161,6 +161,27 @@ __global__ void k_init(typename C::S* out, const double* __restrict__ rho0,
   }
 }
 
+// Seeded initial density rho_mean (1 + a (2u - 1)), u the top 53 bits of
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at state
+// seed + (n + 1) * 0x9E3779B97F4A7C15 for node counter n = i + nx (j + ny k),
+// divided by 2^53.  The arithmetic is IEEE double, each operation rounded
+// on its own (contraction off), so the field equals any other
+// implementation of the same definition bit for bit.
+__global__ void k_seeded_density(double* __restrict__ out, size_t N, uint64_t seed,
+                                 double rho_mean, double amp) {
+#pragma clang fp contract(off)
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + ((uint64_t)n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    const double t = 2.0 * u - 1.0;
+    out[n] = rho_mean * (1.0 + amp * t);
+  }
+}
+
 template <typename C, typename R = typename C::R>
 __global__ void k_get_state(const typename C::S* __restrict__ in, double* __restrict__ st,
                             DevParams<R> P) {
@@ -1508,6 +1529,19 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 size_t lbm_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   return layout(p).total;
+}
+
+int lbm_seeded_density(int32_t nx, int32_t ny, int32_t nz, uint64_t seed, double rho_mean,
+                       double noise_amp, double* rho0, void* stream) {
+  if (!rho0) return fail(LBM_EINVAL, "rho0 is NULL");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
+  if (!(rho_mean > 0.0) || !(noise_amp >= 0.0) || !(noise_amp < 1.0))
+    return fail(LBM_EINVAL, "need rho_mean > 0 and 0 <= noise_amp < 1");
+  const size_t N = (size_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_seeded_density, dim3(grid_for(N, 256)), dim3(256), 0,
+                     (hipStream_t)stream, rho0, N, seed, rho_mean, noise_amp);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
 }
 
 int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const double* rho0,

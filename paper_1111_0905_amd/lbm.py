@@ -102,6 +102,9 @@ def load_library(path: str = _LIB_PATH):
                              ctypes.c_int),
         "lbm_adjoint_init_rho": ([H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
                                  ctypes.c_int),
+        "lbm_seeded_density": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                ctypes.c_void_p], ctypes.c_int),
         "lbm_structure_work_bytes": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
                                      ctypes.c_size_t),
         "lbm_structure_functions": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -211,6 +214,18 @@ def lbm_histogram(h: _Handle, k0: int, k1: int, qx: int, x_range, nx_bins: int, 
                                         ny_bins, _dev_ptr(counts, torch.int64, nx_bins * ny_bins),
                                         ctypes.byref(oor), sums))
     return counts, oor.value, np.array(sums[:])
+
+
+def lbm_seeded_density(nx: int, ny: int, nz: int, seed: int, rho_mean: float, noise_amp: float,
+                       device="cuda", stream=None):
+    """Seeded initial density (nz, ny, nx) float64 on the device (SplitMix64 per node)."""
+    import torch
+    out = torch.empty((nz, ny, nx), dtype=torch.float64, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(load_library().lbm_seeded_density(nx, ny, nz, seed, rho_mean, noise_amp,
+                                             ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 def lbm_structure_functions(h: _Handle, k0: int, k1: int, q: int, r_max: int):
