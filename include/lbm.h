@@ -57,12 +57,12 @@ extern "C" {
 /* storage of the populations; arithmetic is FP64 for LBM_FP64, FP32 else.
  * Bytes per node and buffer: FP64 304, FP32 152, the 16-bit forms 88: the 18
  * moving (f_l, g_l) pairs as 16-bit deviations from the reference pops
- * (round to nearest even), the rest pair in FP64.  The 16-bit forms update
- * the rest pair in remainder form: old value + what the moving pairs gave up
- * in the collision + the rounding residuals of their stores (+ the energy
- * source for g), so the stored mass is conserved to the rounding of small
- * per-node sums, not drifting with the rounding of f_0 (which carries most
- * of the mass). */
+ * (round to nearest even), the rest pair in FP64.  FP32 and the 16-bit forms
+ * update the rest pair in remainder form: old value + what the moving pairs
+ * gave up in the collision (+ the rounding residuals of their 16-bit stores)
+ * (+ the energy source for g), so the stored mass is conserved to the
+ * rounding of small per-node sums instead of drifting with correlated FP32
+ * roundings of the node sums and of f_0 (which carries most of the mass). */
 enum {
   LBM_FP64 = 0,      /* double storage, double arithmetic */
   LBM_FP32 = 1,      /* float storage, float arithmetic */

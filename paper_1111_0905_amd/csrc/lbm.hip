@@ -76,7 +76,7 @@ struct Streamer {
   // fs, gs: collided values of direction l; df, dg: what the collision took
   // from the pair (f_l - fs up to the rounding of fs)
   __device__ __forceinline__ void operator()(int l, R fs, R gs, R df, R dg) {
-    if constexpr (Codec<C>::kResidual) {
+    if constexpr (Codec<C>::kRemainder) {
       rf += df;
       rg += dg;
     }
@@ -101,7 +101,7 @@ struct Streamer {
   // fs, gs: the BGK values of the rest pair; S: the node's energy source
   __device__ __forceinline__ void rest(R fs, R gs, R S) {
     const uint32_t o = node_off(i, j, k, P.nx, P.ny);
-    if constexpr (Codec<C>::kResidual) {  // remainder form: mass kept, energy + S
+    if constexpr (Codec<C>::kRemainder) {  // remainder form: mass kept, energy + S
       T0 f0, g0;
       Codec<C>::ld0(in, o, f0, g0);
       Codec<C>::st0(out, o, f0 + (T0)rf, g0 + (T0)(S + rg));

@@ -76,15 +76,17 @@ struct DevParams {
 //                (pop - pop_ref) rounded to nearest even, direction l >= 1
 //                at words [(l + 3) N, (l + 4) N).
 // The rest population carries most of the mass (f_0 = rho (1 - 2 T_lat)),
-// and the decoded moving populations take few distinct values, so FP32
-// rounding of the node sums and of f_0 is correlated between nodes and steps
-// and would make mass drift.  The 16-bit forms therefore update the rest
-// pair in the remainder form: the new rest value is the old one plus what
-// the 18 moving pairs gave up in the collision plus the rounding residuals
-// of their 16-bit stores (plus the energy source S for g), accumulated in
-// FP32 from small terms and added in FP64 (Streamer::rest).  Stored mass is
-// then conserved to the rounding of those small sums, and the stored energy
-// changes exactly by S and the wall exchange.
+// and in nearly uniform regions (and always for the decoded, quantised
+// moving populations of the 16-bit forms) FP32 roundings of the node sums
+// and of f_0 are correlated between nodes and steps and make mass drift.
+// FP32 and the 16-bit forms therefore update the rest pair in remainder
+// form: the new rest value is the old one plus what the 18 moving pairs gave
+// up in the collision plus (16-bit forms) the rounding residuals of their
+// stores, plus the energy source S for g; the small terms are accumulated in
+// FP32 and added to the rest pair in its storage precision (FP32, or FP64
+// for the 16-bit forms) in Streamer::rest.  Stored mass is then conserved to
+// the rounding of those sums, and the stored energy changes by S and the
+// wall exchange.
 struct F64 { using S = double2; using R = double; };
 struct F32 { using S = float2; using R = float; };
 struct H16 { using S = uint32_t; using R = float; };   // lo: f, hi: g (IEEE half)
@@ -120,14 +122,16 @@ __device__ __forceinline__ uint32_t bf16_rne(float v) {
 }
 
 // Per storage form: enc/dec of one moving pair word, the row of direction
-// l >= 1, and the rest pair (type T0).  kResidual: stores keep the rounding
-// residuals and the rest pair is updated in the remainder form.
+// l >= 1, and the rest pair (type T0).  kRemainder: the rest pair is updated
+// in remainder form (FP32 and the 16-bit forms); kResidual: the moving stores
+// also hand their rounding residuals to it (16-bit forms).
 template <typename C> struct Codec;
 template <> struct Codec<F64> {
   using S = double2;
   using R = double;
   using T0 = double;
   static constexpr bool kResidual = false;
+  static constexpr bool kRemainder = false;
   static __device__ __forceinline__ void dec(S w, R& f, R& g, R, R) { f = w.x; g = w.y; }
   static __device__ __forceinline__ S enc(R f, R g, R, R) { return make_double2(f, g); }
   static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) { return b + (size_t)l * N; }
@@ -144,6 +148,7 @@ template <> struct Codec<F32> {
   using R = float;
   using T0 = float;
   static constexpr bool kResidual = false;
+  static constexpr bool kRemainder = true;
   static __device__ __forceinline__ void dec(S w, R& f, R& g, R, R) { f = w.x; g = w.y; }
   static __device__ __forceinline__ S enc(R f, R g, R, R) { return make_float2(f, g); }
   static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) { return b + (size_t)l * N; }
@@ -161,6 +166,7 @@ struct Dev16 {
   using R = float;
   using T0 = double;
   static constexpr bool kResidual = true;
+  static constexpr bool kRemainder = true;
   static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) {
     return b + (size_t)(l + 3) * N;
   }
