@@ -335,7 +335,9 @@ def main(argv=None):
     elif a.what == "pair":
         for name, rho in (("boiling", a.rho), ("single_phase", a.rho_single)):
             p = cell_params(a.n, rho, a.ra, a.storage, T_c=a.tc)
-            rec = convection(p, seeded_density(a.n, rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
+            rho0, _ = initial_density(p, a.n, rho, a.noise, a.seed)
+            T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
+            rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
             res[name] = _summary(rec, p)
             if rec["ok"]:
                 res[name]["phases"] = phase_statistics(rec["lattice"])
@@ -344,7 +346,9 @@ def main(argv=None):
     elif a.what == "precision":
         for st in ("fp32", "fp16dev", "bf16dev"):
             p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc)
-            rec = convection(p, seeded_density(a.n, a.rho, a.noise, a.seed), a.steps, a.diag, log, a.phase_every)
+            rho0, _ = initial_density(p, a.n, a.rho, a.noise, a.seed)
+            T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
+            rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
             res[st] = _summary(rec, p)
             if rec["ok"]:
                 res[st]["phases"] = phase_statistics(rec["lattice"])
