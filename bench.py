@@ -10,7 +10,7 @@ populations resident in HBM.
 
 Prints one JSON line: MLUPS, ms per step, the roofline of the step kernel
 (algorithmic bytes = one read and one write of each node's stored
-populations: 2 x 152 B in FP32, 2 x 88 B in the 16-bit forms),
+populations: 2 x 152 B in FP32, 2 x 80 B in the 16-bit forms),
 the FP16/BF16-deviation storage forms beside it, and the FP64 CPU oracle
 timed on a bounded sample on the host.
 """
@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + achieved HBM GB/s (% of peak), FP32 vs FP16-storage, 512^3 boiling"
 PEAK_HBM_GBS = 8000.0
 # bytes of one node's populations in one buffer (read once, written once per step)
-NODE_BYTES = {"fp64": 19 * 16, "fp32": 19 * 8, "fp16dev": 18 * 4 + 16, "bf16dev": 18 * 4 + 16}
+NODE_BYTES = {"fp64": 19 * 16, "fp32": 19 * 8, "fp16dev": 18 * 4 + 8, "bf16dev": 18 * 4 + 8}
 
 RA = 1e7                               # Rayleigh number of the boiling cell (Table 1 order)
 

@@ -55,9 +55,9 @@ extern "C" {
 #endif
 
 /* storage of the populations; arithmetic is FP64 for LBM_FP64, FP32 else.
- * Bytes per node and buffer: FP64 304, FP32 152, the 16-bit forms 88: the 18
+ * Bytes per node and buffer: FP64 304, FP32 152, the 16-bit forms 80: the 18
  * moving (f_l, g_l) pairs as 16-bit deviations from the reference pops
- * (round to nearest even), the rest pair in FP64.  FP32 and the 16-bit forms
+ * (round to nearest even), the rest pair in FP32.  FP32 and the 16-bit forms
  * update the rest pair in remainder form: old value + what the moving pairs
  * gave up in the collision (+ the rounding residuals of their 16-bit stores)
  * (+ the energy source for g), so the stored mass is conserved to the

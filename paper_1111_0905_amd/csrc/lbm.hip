@@ -4,7 +4,7 @@
 //
 // Data layout in HBM: structure of arrays of pairs: word l of node (i, j, k)
 // holds (f_l, g_l) at l * N + (k * ny + j) * nx + i (i fastest) for FP64 and
-// FP32; the 16-bit forms keep the rest pair in FP64 ahead of the 18 moving
+// FP32; the 16-bit forms keep the rest pair in FP32 ahead of the 18 moving
 // rows (see the codecs in physics.hpp); two
 // ping-pong buffers hold the post-streaming populations.  Streaming is a push: the collided value of
 // node x in direction l is written to x + c_l of the other buffer; at the
@@ -1085,10 +1085,10 @@ size_t node_bytes(int storage) {
   switch (storage) {
     case LBM_FP64: return Q * 16;
     case LBM_FP32: return Q * 8;
-    default: return (Q - 1) * 4 + 16;   // 18 moving 16-bit pairs + the FP64 rest pair
+    default: return (Q - 1) * 4 + 8;   // 18 moving 16-bit pairs + the FP32 rest pair
   }
 }
-size_t row_bytes(int storage) { return storage == LBM_FP32 ? 8 : 16; }
+size_t row_bytes(int storage) { return storage == LBM_FP64 ? 16 : 8; }
 size_t real_bytes(int storage) { return storage == LBM_FP64 ? 8 : 4; }
 
 constexpr int kDiagBlocks = 1024;
@@ -1577,7 +1577,8 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->cur = 0;
   h->t = 0;
   // defaults from tile/variant sweeps at 512^3 on MI355X: FP32 keeps the next
-  // plane in registers on 32 x 16 tiles, the 16-bit forms on 64 x 8 tiles
+  // plane in registers on 32 x 16 tiles; the 16-bit forms re-read it from
+  // cache on 64 x 16 tiles
   h->kernel = p->kernel;
   if (p->tile_x == 0 && p->tile_y == 0) {
     if (p->storage == LBM_FP64) {
@@ -1588,7 +1589,8 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
       h->tile_y = 16;
     } else {
       h->tile_x = 64;
-      h->tile_y = 8;
+      h->tile_y = 16;
+      if (p->kernel == LBM_KERNEL_FUSED) h->kernel = LBM_KERNEL_FUSED_RELOAD;
     }
   } else {
     h->tile_x = p->tile_x ? p->tile_x : 64;

@@ -71,10 +71,10 @@ struct DevParams {
 // f*_l and g*_l to the same node, also at the walls).  Stored as S, computed
 // in R.  Buffer layout, structure of arrays (N nodes, node offset i):
 //   FP64, FP32:  direction l at words [l N, (l + 1) N).
-//   FP16, BF16:  the rest pair (l = 0) in FP64 (absolute values, N double2
-//                in 32-bit words [0, 4 N)); the 18 moving directions hold
+//   FP16, BF16:  the rest pair (l = 0) in FP32 (absolute values, N float2
+//                in 32-bit words [0, 2 N)); the 18 moving directions hold
 //                (pop - pop_ref) rounded to nearest even, direction l >= 1
-//                at words [(l + 3) N, (l + 4) N).
+//                at words [(l + 1) N, (l + 2) N).
 // The rest population carries most of the mass (f_0 = rho (1 - 2 T_lat)),
 // and in nearly uniform regions (and always for the decoded, quantised
 // moving populations of the 16-bit forms) FP32 roundings of the node sums
@@ -83,10 +83,9 @@ struct DevParams {
 // form: the new rest value is the old one plus what the 18 moving pairs gave
 // up in the collision plus (16-bit forms) the rounding residuals of their
 // stores, plus the energy source S for g; the small terms are accumulated in
-// FP32 and added to the rest pair in its storage precision (FP32, or FP64
-// for the 16-bit forms) in Streamer::rest.  Stored mass is then conserved to
-// the rounding of those sums, and the stored energy changes by S and the
-// wall exchange.
+// FP32 and added to the FP32 rest pair in Streamer::rest.  Stored mass is
+// then conserved to the rounding of those sums, and the stored energy changes
+// by S and the wall exchange.
 struct F64 { using S = double2; using R = double; };
 struct F32 { using S = float2; using R = float; };
 struct H16 { using S = uint32_t; using R = float; };   // lo: f, hi: g (IEEE half)
@@ -164,20 +163,20 @@ template <> struct Codec<F32> {
 struct Dev16 {
   using S = uint32_t;
   using R = float;
-  using T0 = double;
+  using T0 = float;
   static constexpr bool kResidual = true;
   static constexpr bool kRemainder = true;
   static __device__ __forceinline__ const S* row(const S* b, int l, size_t N) {
-    return b + (size_t)(l + 3) * N;
+    return b + (size_t)(l + 1) * N;
   }
-  static __device__ __forceinline__ S* row(S* b, int l, size_t N) { return b + (size_t)(l + 3) * N; }
+  static __device__ __forceinline__ S* row(S* b, int l, size_t N) { return b + (size_t)(l + 1) * N; }
   static __device__ __forceinline__ void ld0(const S* b, uint32_t i, T0& f, T0& g) {
-    const double2 w = at32((const double2*)b, i);
+    const float2 w = at32((const float2*)b, i);
     f = w.x;
     g = w.y;
   }
   static __device__ __forceinline__ void st0(S* b, uint32_t i, T0 f, T0 g) {
-    at32((double2*)b, i) = make_double2(f, g);
+    at32((float2*)b, i) = make_float2(f, g);
   }
 };
 template <> struct Codec<H16> : Dev16 {

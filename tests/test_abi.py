@@ -67,21 +67,21 @@ def test_null_handle_is_rejected(lib):
 
 def test_largest_lattices(lib):
     """Every direction's array must stay below 4 GiB (32-bit node offsets):
-    the widest row holds 8 B per node in FP32 and 16 B in FP64 and in the
-    16-bit forms (their FP64 rest pair)."""
+    the widest row holds 8 B per node in FP32 and the 16-bit forms (their
+    FP32 rest pair) and 16 B in FP64."""
     from paper_1111_0905_amd import lbm
     assert lbm.lbm_workspace_bytes(lbm.Params(812, 812, 812, storage=lbm.LBM_FP32)) > 0
     with pytest.raises(lbm.LbmError):
         lbm.lbm_workspace_bytes(lbm.Params(813, 813, 813, storage=lbm.LBM_FP32))
-    for st in (lbm.LBM_FP64, lbm.LBM_FP16DEV):   # 16 B per node in the widest row
-        assert lbm.lbm_workspace_bytes(lbm.Params(645, 645, 645, storage=st, rho_ref=1.0,
-                                                  T_ref=0.05)) > 0
-        with pytest.raises(lbm.LbmError):
-            lbm.lbm_workspace_bytes(lbm.Params(646, 646, 646, storage=st, rho_ref=1.0, T_ref=0.05))
-    # 16-bit forms: 88 B per node and buffer (FP64 rest pair + 18 words)
+    assert lbm.lbm_workspace_bytes(lbm.Params(812, 812, 812, storage=lbm.LBM_FP16DEV,
+                                              rho_ref=1.0, T_ref=0.05)) > 0
+    assert lbm.lbm_workspace_bytes(lbm.Params(645, 645, 645, storage=lbm.LBM_FP64)) > 0
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes(lbm.Params(646, 646, 646, storage=lbm.LBM_FP64))
+    # 16-bit forms: 80 B per node and buffer (FP32 rest pair + 18 words)
     w16 = lbm.lbm_workspace_bytes(lbm.Params(512, 512, 512, storage=lbm.LBM_FP16DEV,
                                              rho_ref=1.0, T_ref=0.05))
-    assert w16 >= 2 * 88 * 512 ** 3
+    assert w16 >= 2 * 80 * 512 ** 3
 
 
 def test_null_arguments_of_diagnostics(lib):

@@ -105,7 +105,7 @@ G = eos.coupling_for_tc(TC)
 # after 3000 steps the interface is still relaxing (densities about 1 % from
 # the Maxwell values), so the bars are on agreement with the oracle's state
 # at that time, which the slow relaxation makes sensitive to rounding
-SLAB_BARS = {"fp32": 2e-5, "fp16dev": 3e-3, "bf16dev": 5e-3}
+SLAB_BARS = {"fp32": 2e-5, "fp16dev": 3e-3, "bf16dev": 1e-2}
 
 
 def _slab_params(glbm, storage, T, rg, rl):
@@ -151,7 +151,7 @@ def test_coexistence_densities(glbm, slab, storage):
 
 BUB_N = 32
 BUB_STEPS = 600
-MASS_BARS = {"fp32": 1e-7, "fp16dev": 1e-10, "bf16dev": 1e-10}
+MASS_BARS = {"fp32": 1e-7, "fp16dev": 1e-9, "bf16dev": 1e-9}
 
 
 def _bubble_volumes(rho, thr):
@@ -205,9 +205,8 @@ def test_bubble_volume_statistics(glbm, bubbles, storage):
     got = _bubble_volumes(fl[0].cpu().numpy(), thr)
     drift = abs(tot[0] / rho0.sum() - 1)
     print(f"{storage}: bubble volumes {got} vs oracle {want}; mass drift {drift:.1e}")
-    # every storage form updates its rest pair in remainder form: mass is
-    # conserved to the rounding of small per-node sums (FP32 rest pair: to
-    # its own rounding too; FP64 rest pair of the 16-bit forms: below that)
+    # every storage form updates its FP32 rest pair in remainder form: mass is
+    # conserved to the rounding of small per-node sums and of the rest pair
     assert drift < MASS_BARS[storage]
     assert len(got) == len(want)
     assert max(abs(a / b - 1) for a, b in zip(got, want)) < 0.05
