@@ -47,7 +47,9 @@ rules.  The readings used here (each stated where it is used) are:
 * half-way bounce-back for f and anti-bounce-back for g at the walls, which
   sit half a lattice spacing below k = 0 and above k = nz - 1;
 * ghost planes at the walls for the gradient stencils: psi from the mirror
-  image of rho (neutral wetting); E and rho in the thermal force and in S
+  image of rho (neutral wetting), or, where a wall density is given (the
+  paper is silent on wettability), psi of that density; E and rho in the
+  thermal force and in S
   extrapolated linearly through the wall (a conductive state at rest is then
   an exact steady state with Nu = 1).
 
@@ -112,6 +114,12 @@ class Params:
     rho_kappa: float = 0.5
     periodic_z: bool = False
     T_lat: float = 0.0          # lattice temperature of f^eq; 0 -> (T_d + T_u) / 2
+    # wetting (the paper is silent on wettability): a wall density > 0 gives
+    # the psi ghost plane beyond that wall the constant psi(rho_wall), the
+    # wall-density method of Benzi et al., Phys. Rev. E 74, 021509 (2006);
+    # <= 0 mirrors psi of the wall plane (neutral wetting)
+    rho_wall_d: float = 0.0
+    rho_wall_u: float = 0.0
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)
@@ -200,11 +208,29 @@ def _grad_w(p: Params, a: torch.Tensor, ghost: str = "mirror") -> torch.Tensor:
     return s
 
 
+def _grad_w_psi(p: Params, psi: torch.Tensor) -> torch.Tensor:
+    """W-stencil gradient of psi; at a wall with a prescribed density the
+    ghost plane holds psi(rho_wall), elsewhere the mirror image."""
+    if p.periodic_z or (p.rho_wall_d <= 0 and p.rho_wall_u <= 0):
+        return _grad_w(p, psi)
+    ap = _pad_z(psi, walls=True, odd=False)
+    lo, mid, hi = ap[..., :1, :, :], ap[..., 1:-1, :, :], ap[..., -1:, :, :]
+    if p.rho_wall_d > 0:
+        lo = torch.full_like(lo, math.exp(-1.0 / p.rho_wall_d))
+    if p.rho_wall_u > 0:
+        hi = torch.full_like(hi, math.exp(-1.0 / p.rho_wall_u))
+    ap = torch.cat([lo, mid, hi], dim=-3)
+    s = torch.zeros((3,) + tuple(psi.shape), dtype=psi.dtype)
+    for l in range(1, Q19):
+        s = s + W_FOR[l] * C[l].view(3, 1, 1, 1) * _at(ap, C_INT[l])
+    return s
+
+
 def sc_force(p: Params, rho: torch.Tensor, G=None) -> torch.Tensor:
     """eq. (FORCE): F_SC = -G psi(x) sum_l W_l c_l psi(x + c_l)."""
     G = p.G if G is None else G
     psi = pseudopotential(rho)
-    return -G * psi * _grad_w(p, psi)
+    return -G * psi * _grad_w_psi(p, psi)
 
 
 def forces(p: Params, rho, E, G=None):
