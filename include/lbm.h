@@ -126,6 +126,13 @@ typedef struct lbm_params {
   double rho_kappa;
   double rho_ref, T_ref;
   double T_lat;        /* lattice temperature of f^eq; <= 0 picks (T_d + T_u) / 2 */
+  double rho_wall_d;   /* wetting of the bottom wall: > 0 gives the psi ghost plane below
+                          k = 0 the constant value psi(rho_wall_d) (a prescribed wall
+                          density); <= 0 mirrors psi of the wall plane (neutral wetting,
+                          90 degree contact angle).  The paper is silent on wettability;
+                          this is the wall-density method of Benzi et al., Phys. Rev. E 74,
+                          021509 (2006).  Ignored with periodic_z. */
+  double rho_wall_u;   /* the same for the top wall (ghost plane above k = nz - 1) */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

@@ -236,7 +236,8 @@ __global__ void k_rhoE(const typename C::S* __restrict__ in, R* __restrict__ srh
 }
 
 // Neighbour values from scratch with the wall ghosts: psi from the mirrored
-// density, rho and E extrapolated linearly through the wall.
+// density (or the prescribed wall density), rho and E extrapolated linearly
+// through the wall.
 template <typename R>
 struct ScratchNb {
   const R* srho;
@@ -260,6 +261,7 @@ struct ScratchNb {
     }
     const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
     const int ki = kk < 0 ? 1 : nz - 2;     // next plane inside
+    if (which == 0 && (kk < 0 ? P.wet_d : P.wet_u)) return kk < 0 ? P.psi_wd : P.psi_wu;
     const R v0 = a[node_off(ii, jj, kw, nx, ny)];
     if (which == 0) return psi_of<R>(v0);
     const R v1 = a[node_off(ii, jj, ki, nx, ny)];
@@ -403,10 +405,11 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       sPsi[s][ring_s] = psi_of<R>(rho);
     }
   };
-  // wall ghost plane: psi mirrored, rho and E extrapolated linearly
-  auto ghost = [&](int sg, int sw, int si) {
+  // wall ghost plane: psi mirrored (or that of the prescribed wall density),
+  // rho and E extrapolated linearly
+  auto ghost = [&](int sg, int sw, int si, int wet, R psi_w) {
     for (int q = t; q < PN; q += NT) {
-      sPsi[sg][q] = sPsi[sw][q];
+      sPsi[sg][q] = wet ? psi_w : sPsi[sw][q];
       sRho[sg][q] = R(2) * sRho[sw][q] - sRho[si][q];
       sE[sg][q] = R(2) * sE[sw][q] - sE[si][q];
     }
@@ -429,8 +432,8 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       fill(0, slot(kn), wb, wb0f, wb0g);
     __syncthreads();
     if (walls && (k == 0 || kn == nz)) {
-      if (k == 0) ghost(slot(-1), slot(0), slot(1));
-      if (kn == nz) ghost(slot(kn), slot(k), slot(k - 1));
+      if (k == 0) ghost(slot(-1), slot(0), slot(1), P.wet_d, P.psi_wd);
+      if (kn == nz) ghost(slot(kn), slot(k), slot(k - 1), P.wet_u, P.psi_wu);
       __syncthreads();
     }
     if (active) {
@@ -992,14 +995,16 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const R* __restrict__ srho,
       }
       if (!P.periodic_z) {
         // ghosts: a node x on a wall plane reading direction l across the
-        // wall sees psi of the wall-plane node (mirror) and 2 a(wall plane)
+        // wall sees psi of the wall-plane node (mirror; a constant, with no
+        // adjoint, for a prescribed wall density) and 2 a(wall plane)
         // - a(next plane) for E and rho (linear extrapolation)
         const int kw = CZ[l] < 0 ? 0 : P.nz - 1;
         const int ki = CZ[l] < 0 ? 1 : P.nz - 2;
+        const int wet = CZ[l] < 0 ? P.wet_d : P.wet_u;
         if (CZ[l] != 0 && (k == kw || k == ki)) {
           const size_t o = ((size_t)kw * P.ny + jx) * P.nx + ix;
           if (k == kw) {
-            pb += W * wdot(gbar, N, 0, o, l);
+            if (!wet) pb += W * wdot(gbar, N, 0, o, l);
             eb += R(2) * W * wdot(gbar, N, 1, o, l);
             qb += R(2) * W * wdot(gbar, N, 2, o, l);
           }
@@ -1117,6 +1122,8 @@ int validate(const lbm_params* p) {
   if (!(p->c_v > 0.0) || !(p->rho_kappa > 0.0)) return fail(LBM_EINVAL, "c_v and rho_kappa must be > 0");
   if (!(p->T_d > 0.0) || !(p->T_u > 0.0)) return fail(LBM_EINVAL, "wall temperatures must be > 0");
   if (!isfinite(p->gravity)) return fail(LBM_EINVAL, "gravity must be finite");
+  if (!isfinite(p->rho_wall_d) || !isfinite(p->rho_wall_u))
+    return fail(LBM_EINVAL, "wall densities must be finite");
   if (p->storage >= LBM_FP16DEV && (!(p->rho_ref > 0.0) || !(p->T_ref > 0.0)))
     return fail(LBM_EINVAL, "16-bit storage needs rho_ref > 0 and T_ref > 0");
   return LBM_OK;
@@ -1183,6 +1190,10 @@ DevParams<R> dev_params(const lbm_params& p) {
   d.T_u = (R)p.T_u;
   const double T_lat = p.T_lat > 0.0 ? p.T_lat : 0.5 * (p.T_d + p.T_u);
   d.T_lat = (R)T_lat;
+  d.wet_d = p.rho_wall_d > 0.0 ? 1 : 0;
+  d.wet_u = p.rho_wall_u > 0.0 ? 1 : 0;
+  d.psi_wd = (R)(d.wet_d ? exp(-1.0 / p.rho_wall_d) : 0.0);
+  d.psi_wu = (R)(d.wet_u ? exp(-1.0 / p.rho_wall_u) : 0.0);
   const bool dev = p.storage >= LBM_FP16DEV;
   for (int l = 0; l < Q; ++l) {
     // reference populations: equilibrium at rest of (rho_ref, T_ref)

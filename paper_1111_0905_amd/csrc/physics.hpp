@@ -63,6 +63,10 @@ struct DevParams {
   R T_d, T_u;
   R T_lat;              // lattice temperature of f^eq
   R fref[Q], gref[Q];   // deviation references (16-bit storage only)
+  // psi of the ghost planes at the bottom / top wall when wet_d / wet_u
+  // (prescribed wall density); otherwise the mirror image of the wall plane
+  int wet_d, wet_u;
+  R psi_wd, psi_wu;
 };
 
 // ----------------------------------------------------------- storage codecs

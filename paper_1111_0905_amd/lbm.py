@@ -39,6 +39,7 @@ class _CParams(ctypes.Structure):
         ("T_d", ctypes.c_double), ("T_u", ctypes.c_double), ("gravity", ctypes.c_double),
         ("c_v", ctypes.c_double), ("rho_kappa", ctypes.c_double),
         ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("T_lat", ctypes.c_double),
+        ("rho_wall_d", ctypes.c_double), ("rho_wall_u", ctypes.c_double),
     ]
 
 
@@ -66,6 +67,8 @@ class Params:
     rho_ref: float = 1.0
     T_ref: float = 0.045
     T_lat: float = 0.0
+    rho_wall_d: float = 0.0
+    rho_wall_u: float = 0.0
 
     def c(self) -> _CParams:
         return _CParams(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -103,6 +103,65 @@ def test_ragged_shapes_fp64(glbm, shape, periodic):
     assert err < 1e-12, err
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_force_form_coupling_matches_oracle(glbm, storage):
+    """The force-form reading of the temperature coupling: the standard
+    isothermal equilibrium (lattice temperature 1/3) with the whole non-ideal
+    part of the ideal pressure, -grad[rho (T - 1/3)], applied as a force on the
+    W stencil.  It is the same scheme with T_lat = 1/3; 24^3, walls, gravity,
+    spinodal mean density, 100 steps."""
+    n = 24
+    print(f"case: 24^3 {storage} T_lat = 1/3, 100 steps", flush=True)
+    rho0 = synth.noisy_density(n, n, n, _mean_density(), 0.01, 1234)
+    kw = _kw(T_lat=1.0 / 3.0)
+    o = _oracle_state(n, n, n, rho0, 100, **kw)
+    if storage == "fp64":
+        lat = _gpu(glbm, n, n, n, rho0, 100, glbm.LBM_FP64, **kw)
+        err = _rel(lat.state().cpu().numpy(), o.state().numpy())
+        print(f"max rel state err {err:.3e}")
+        assert err < 1e-12
+    else:
+        lat = _gpu(glbm, n, n, n, rho0, 100, glbm.LBM_FP32, **kw)
+        _, fl = lat.fields()
+        fl = fl.cpu().numpy()
+        of = o.fields()
+        e_rho = _rel(fl[0], of["rho"].numpy())
+        e_T = _rel(fl[4], of["T"].numpy())
+        e_v = float(np.abs(fl[1:4] - of["v"].numpy()).max() / np.abs(of["v"].numpy()).max())
+        print(f"FP32 errors: rho {e_rho:.2e} v {e_v:.2e} T {e_T:.2e}")
+        assert e_rho < fp32_tolerance() and e_T < fp32_tolerance()
+        assert e_v < 10 * fp32_tolerance()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_wetting_walls_match_oracle(glbm, storage):
+    """Prescribed wall densities for the psi ghost planes (liquid-like at the
+    bottom, vapour-like at the top): 20 x 12 x 16, spinodal mean density,
+    60 steps, every kernel the default picks plus the two-pass reference."""
+    nx, ny, nz = 20, 12, 16
+    rg, rl, _ = eos.maxwell(0.9 * TC, G)
+    rho0 = synth.noisy_density(nx, ny, nz, _mean_density(), 0.02, 77)
+    kw = _kw(rho_wall_d=rl, rho_wall_u=rg)
+    print(f"case: wetting walls {storage}", flush=True)
+    o = _oracle_state(nx, ny, nz, rho0, 60, **kw)
+    st = glbm.LBM_FP64 if storage == "fp64" else glbm.LBM_FP32
+    for kernel in (0, 1):
+        lat = _gpu(glbm, nx, ny, nz, rho0, 60, st, kernel=kernel, **kw)
+        if storage == "fp64":
+            err = _rel(lat.state().cpu().numpy(), o.state().numpy())
+            print(f"kernel {kernel}: max rel state err {err:.3e}")
+            assert err < 1e-12
+        else:
+            _, fl = lat.fields()
+            fl = fl.cpu().numpy()
+            e_rho = _rel(fl[0], o.fields()["rho"].numpy())
+            print(f"kernel {kernel}: FP32 rho err {e_rho:.2e}")
+            assert e_rho < fp32_tolerance()
+    # the walls matter: the same run with neutral walls differs
+    o_n = _oracle_state(nx, ny, nz, rho0, 60, **_kw())
+    assert _rel(o_n.state().numpy(), o.state().numpy()) > 1e-4
+
+
 def test_kernel_variants_agree_fp64(glbm):
     nx, ny, nz = 70, 19, 23
     rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 11)
