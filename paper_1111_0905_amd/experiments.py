@@ -316,15 +316,20 @@ def main(argv=None):
     ap.add_argument("--phase-every", type=int, default=0,
                     help="steps between bubble statistics (0: only at the end)")
     ap.add_argument("--tc", type=float, default=TC)
+    ap.add_argument("--rho-wall-d", type=float, default=0.0,
+                    help="wall density of the bottom wall's psi ghost (wetting); 0 = neutral")
+    ap.add_argument("--rho-wall-u", type=float, default=0.0,
+                    help="the same for the top wall")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    walls = dict(rho_wall_d=a.rho_wall_d, rho_wall_u=a.rho_wall_u)
     lbm.load_library()
     res = {}
     log = sys.stderr
     if a.rho is None:
         a.rho = boiling_density(a.n, a.ra, T_c=a.tc, margin=a.margin)
     if a.what == "convection":
-        p = cell_params(a.n, a.rho, a.ra, a.storage, T_c=a.tc)
+        p = cell_params(a.n, a.rho, a.ra, a.storage, T_c=a.tc, **walls)
         rho0, hydro = initial_density(p, a.n, a.rho, a.noise, a.seed)
         T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
         rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
@@ -334,7 +339,7 @@ def main(argv=None):
             res["phases"] = phase_statistics(rec["lattice"])
     elif a.what == "pair":
         for name, rho in (("boiling", a.rho), ("single_phase", a.rho_single)):
-            p = cell_params(a.n, rho, a.ra, a.storage, T_c=a.tc)
+            p = cell_params(a.n, rho, a.ra, a.storage, T_c=a.tc, **walls)
             rho0, _ = initial_density(p, a.n, rho, a.noise, a.seed)
             T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
             rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
@@ -345,7 +350,7 @@ def main(argv=None):
             torch.cuda.empty_cache()
     elif a.what == "precision":
         for st in ("fp32", "fp16dev", "bf16dev"):
-            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc)
+            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc, **walls)
             rho0, _ = initial_density(p, a.n, a.rho, a.noise, a.seed)
             T0 = initial_temperature(p, a.n, a.tnoise, a.seed) if a.tnoise > 0 else None
             rec = convection(p, rho0, a.steps, a.diag, log, a.phase_every, T0)
@@ -367,7 +372,7 @@ def main(argv=None):
         out = {}
         d = torch.from_numpy(synth.random_unit_field(a.n, a.n, a.n, 7)).cuda().reshape(-1)
         for st in ("fp32", "fp64"):
-            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc)
+            p = cell_params(a.n, a.rho, a.ra, st, T_c=a.tc, **walls)
             rho0 = seeded_density(a.n, a.rho, a.noise, a.seed)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
