@@ -162,6 +162,46 @@ def test_wetting_walls_match_oracle(glbm, storage):
     assert _rel(o_n.state().numpy(), o.state().numpy()) > 1e-4
 
 
+PACKED_BARS = {"fp32": 1e-5, "fp16dev": 2e-4, "bf16dev": 2e-3}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev", "bf16dev"])
+@pytest.mark.parametrize("shape", [(65, 9, 13), (3, 17, 5), (130, 33, 4)])
+def test_ragged_shapes_packed(glbm, storage, shape):
+    """Ragged tiles (partial in x and y, and fewer planes than a z chunk)
+    for the FP32 and 16-bit storage forms with their default kernels, against
+    the FP64 oracle: density and temperature fields after 20 steps within the
+    storage form's bar."""
+    nx, ny, nz = shape
+    print(f"case: ragged packed {shape} {storage}", flush=True)
+    rho_m = _mean_density()
+    rho0 = synth.noisy_density(nx, ny, nz, rho_m, 0.02, 31)
+    kw = _kw(tau_nu=0.8, tau_kappa=0.7, gravity=1e-4)
+    o = _oracle_state(nx, ny, nz, rho0, 20, **kw)
+    st = {"fp32": glbm.LBM_FP32, "fp16dev": glbm.LBM_FP16DEV, "bf16dev": glbm.LBM_BF16DEV}[storage]
+    lat = _gpu(glbm, nx, ny, nz, rho0, 20, st, rho_ref=rho_m, T_ref=0.9 * TC, **kw)
+    _, fl = lat.fields()
+    fl = fl.cpu().numpy()
+    of = o.fields()
+    e_rho = _rel(fl[0], of["rho"].numpy())
+    e_T = _rel(fl[4], of["T"].numpy())
+    print(f"{storage} {shape}: rho {e_rho:.2e} T {e_T:.2e}")
+    assert e_rho < PACKED_BARS[storage] and e_T < PACKED_BARS[storage]
+
+
+def test_single_plane_periodic_fp64(glbm):
+    """nz = 1 with periodic z: every z-moving population returns to its own
+    plane."""
+    nx, ny, nz = 24, 10, 1
+    print("case: single plane periodic", flush=True)
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 41)
+    kw = _kw(tau_nu=0.8, tau_kappa=0.7, gravity=1e-4)
+    o = _oracle_state(nx, ny, nz, rho0, 8, periodic_z=1, **kw)
+    lat = _gpu(glbm, nx, ny, nz, rho0, 8, glbm.LBM_FP64, periodic_z=1, **kw)
+    err = _rel(lat.state().cpu().numpy(), o.state().numpy())
+    assert err < 1e-12, err
+
+
 def test_kernel_variants_agree_fp64(glbm):
     nx, ny, nz = 70, 19, 23
     rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 11)
