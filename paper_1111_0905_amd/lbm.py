@@ -167,6 +167,9 @@ def lbm_init(p: Params, rho0, T0=None, stream=None) -> _Handle:
     if ws.data_ptr() % 256:
         raise LbmError(-2, "torch workspace not 256-byte aligned")
     stream = stream if stream is not None else torch.cuda.current_stream(rho0.device)
+    # the handle's work runs on `stream`: tell torch's caching allocator, so the
+    # workspace is not handed out again before that work has finished
+    ws.record_stream(stream)
     h = ctypes.c_void_p()
     cp = p.c()
     T0p = _dev_ptr(T0, torch.float64, p.n) if T0 is not None else None
