@@ -92,3 +92,57 @@ def latent_heat(T: float, rho_g: float, rho_l: float) -> float:
 def nonideal_energy(rho: float, G: float) -> float:
     """integral of P_NI / rho^2 d rho with P_NI = (G/2) exp(-2/rho)."""
     return 0.25 * G * math.exp(-2.0 / rho)
+
+
+# ---------------------------------------------------------------- psi forms
+
+def psi_sc(rho: float) -> float:
+    """The original Shan-Chen pseudopotential 1 - exp(-rho)."""
+    return 1.0 - math.exp(-rho)
+
+
+def pressure_sc(rho: float, T: float, G: float) -> float:
+    """Bulk EOS with psi = 1 - exp(-rho): P = rho T + (G/2) psi^2."""
+    return rho * T + 0.5 * G * psi_sc(rho) ** 2
+
+
+def dp_drho_sc(rho: float, T: float, G: float) -> float:
+    return T + G * psi_sc(rho) * math.exp(-rho)
+
+
+def critical_point_sc(G: float):
+    """d2P/drho2 = G exp(-rho) (2 exp(-rho) - 1) = 0 at rho_c = ln 2, where
+    dP/drho = 0 gives T_c = -G/4.  Returns (rho_c, T_c)."""
+    return math.log(2.0), -G / 4.0
+
+
+def coexistence_sc(T: float, G: float, rule: str = "mechanical"):
+    """(rho_g, rho_l, P) of the psi = 1 - exp(-rho) fluid at temperature T:
+    equal pressures and a zero area integral_{rho_g}^{rho_l} (P - P(rho)) w(rho)
+    d rho, with w = psi'/psi (the mechanical-stability rule of a
+    pseudopotential fluid whose forcing stencil adds no correction, which
+    for psi = exp(-1/rho) is Maxwell's 1/rho^2) or, with rule "maxwell",
+    w = 1/rho^2."""
+    if rule == "mechanical":
+        w = lambda r: math.exp(-r) / psi_sc(r)
+    else:
+        w = lambda r: 1.0 / (r * r)
+    rc, tc = critical_point_sc(G)
+    if not T < tc:
+        raise ValueError("no coexistence above T_c")
+    sg = brentq(dp_drho_sc, 1e-6, rc, args=(T, G), xtol=1e-15)
+    sl = brentq(dp_drho_sc, rc, 50.0, args=(T, G), xtol=1e-15)
+    p_lo = max(pressure_sc(sl, T, G), 1e-14)
+    p_hi = pressure_sc(sg, T, G)
+
+    def dens(P, lo, hi):
+        return brentq(lambda r: pressure_sc(r, T, G) - P, lo, hi, xtol=1e-15, rtol=1e-15)
+
+    def area(P):
+        rg, rl = dens(P, 0.0, sg), dens(P, sl, 200.0)
+        val, _ = quad(lambda r: (P - pressure_sc(r, T, G)) * w(r), rg, rl,
+                      epsabs=1e-14, epsrel=1e-13, limit=200)
+        return val
+
+    P = brentq(area, p_lo * (1 + 1e-12), p_hi * (1 - 1e-12), xtol=1e-16, rtol=1e-14)
+    return dens(P, 0.0, sg), dens(P, sl, 200.0), P

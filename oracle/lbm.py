@@ -120,6 +120,11 @@ class Params:
     # <= 0 mirrors psi of the wall plane (neutral wetting)
     rho_wall_d: float = 0.0
     rho_wall_u: float = 0.0
+    # form of the pseudopotential: 0 = exp(-1/rho), the paper's choice; 1 =
+    # 1 - exp(-rho), the original Shan-Chen form, one of the alternatives the
+    # paper names as prior art (its coexistence follows the mechanical rule of
+    # that psi, not Maxwell's)
+    psi_form: int = 0
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)
@@ -178,10 +183,16 @@ def hydro_moments(f: torch.Tensor, g: torch.Tensor):
     return rho, j, E
 
 
-def pseudopotential(rho: torch.Tensor) -> torch.Tensor:
+def pseudopotential(rho: torch.Tensor, form: int = 0) -> torch.Tensor:
     """psi[rho] = exp(-1/rho), the choice the paper makes for thermodynamic
-    consistency."""
+    consistency (form 0), or the original Shan-Chen 1 - exp(-rho) (form 1)."""
+    if form == 1:
+        return 1.0 - torch.exp(-rho)
     return torch.exp(-1.0 / rho)
+
+
+def _psi_scalar(rho: float, form: int) -> float:
+    return 1.0 - math.exp(-rho) if form == 1 else math.exp(-1.0 / rho)
 
 
 def _pad_z_linear(a: torch.Tensor, walls: bool) -> torch.Tensor:
@@ -216,9 +227,9 @@ def _grad_w_psi(p: Params, psi: torch.Tensor) -> torch.Tensor:
     ap = _pad_z(psi, walls=True, odd=False)
     lo, mid, hi = ap[..., :1, :, :], ap[..., 1:-1, :, :], ap[..., -1:, :, :]
     if p.rho_wall_d > 0:
-        lo = torch.full_like(lo, math.exp(-1.0 / p.rho_wall_d))
+        lo = torch.full_like(lo, _psi_scalar(p.rho_wall_d, p.psi_form))
     if p.rho_wall_u > 0:
-        hi = torch.full_like(hi, math.exp(-1.0 / p.rho_wall_u))
+        hi = torch.full_like(hi, _psi_scalar(p.rho_wall_u, p.psi_form))
     ap = torch.cat([lo, mid, hi], dim=-3)
     s = torch.zeros((3,) + tuple(psi.shape), dtype=psi.dtype)
     for l in range(1, Q19):
@@ -229,7 +240,7 @@ def _grad_w_psi(p: Params, psi: torch.Tensor) -> torch.Tensor:
 def sc_force(p: Params, rho: torch.Tensor, G=None) -> torch.Tensor:
     """eq. (FORCE): F_SC = -G psi(x) sum_l W_l c_l psi(x + c_l)."""
     G = p.G if G is None else G
-    psi = pseudopotential(rho)
+    psi = pseudopotential(rho, p.psi_form)
     return -G * psi * _grad_w_psi(p, psi)
 
 
