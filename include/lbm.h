@@ -133,6 +133,11 @@ typedef struct lbm_params {
                           this is the wall-density method of Benzi et al., Phys. Rev. E 74,
                           021509 (2006).  Ignored with periodic_z. */
   double rho_wall_u;   /* the same for the top wall (ghost plane above k = nz - 1) */
+  int32_t psi_form;    /* pseudopotential of eq. (FORCE): 0 = exp(-1/rho), the paper's choice
+                          (coexistence on the Maxwell construction); 1 = 1 - exp(-rho), the
+                          original Shan-Chen form, one of the alternatives the paper cites as
+                          prior art (coexistence on its own mechanical-stability rule).
+                          Other values: LBM_EINVAL */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;

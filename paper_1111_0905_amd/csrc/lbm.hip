@@ -252,18 +252,18 @@ struct ScratchNb {
     const R* a = which == 2 ? sE : srho;
     if (kk >= 0 && kk < nz) {
       const R v = a[node_off(ii, jj, kk, nx, ny)];
-      return which == 0 ? psi_of<R>(v) : v;
+      return which == 0 ? psi_of<R>(v, P.psi_form) : v;
     }
     if (P.periodic_z) {
       kk = kk < 0 ? kk + nz : kk - nz;
       const R v = a[node_off(ii, jj, kk, nx, ny)];
-      return which == 0 ? psi_of<R>(v) : v;
+      return which == 0 ? psi_of<R>(v, P.psi_form) : v;
     }
     const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
     const int ki = kk < 0 ? 1 : nz - 2;     // next plane inside
     if (which == 0 && (kk < 0 ? P.wet_d : P.wet_u)) return kk < 0 ? P.psi_wd : P.psi_wu;
     const R v0 = a[node_off(ii, jj, kw, nx, ny)];
-    if (which == 0) return psi_of<R>(v0);
+    if (which == 0) return psi_of<R>(v0, P.psi_form);
     const R v1 = a[node_off(ii, jj, ki, nx, ny)];
     return R(2) * v0 - v1;
   }
@@ -278,7 +278,7 @@ __device__ __forceinline__ Macro<R> macro_from_scratch(const R* f, const R* g, c
   grad_w<R>([&](int l) { return nb.get(0, l); }, gpx, gpy, gpz);
   grad_w<R>([&](int l) { return nb.get(2, l); }, gEx, gEy, gEz);
   grad_w<R>([&](int l) { return nb.get(1, l); }, grx, gry, grz);
-  return node_macro<R>(f, g, rho, E, psi_of<R>(rho), gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
+  return node_macro<R>(f, g, rho, E, psi_of<R>(rho, P.psi_form), gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
 }
 
 template <typename C, typename R = typename C::R>
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       }
       sRho[s][own_s] = rho;
       sE[s][own_s] = E;
-      sPsi[s][own_s] = psi_of<R>(rho);
+      sPsi[s][own_s] = psi_of<R>(rho, P.psi_form);
     }
     for (int r = t; r < nring; r += NT) {
       int rx, ry;
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
       moments<R>(fr, gr, rho, E);
       sRho[s][ring_s] = rho;
       sE[s][ring_s] = E;
-      sPsi[s][ring_s] = psi_of<R>(rho);
+      sPsi[s][ring_s] = psi_of<R>(rho, P.psi_form);
     }
   };
   // wall ghost plane: psi mirrored (or that of the prescribed wall density),
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st
     grad_w<R>([&](int l) { return nb.get(0, l); }, gpx, gpy, gpz);
     grad_w<R>([&](int l) { return nb.get(2, l); }, gEx, gEy, gEz);
     grad_w<R>([&](int l) { return nb.get(1, l); }, grx, gry, grz);
-    const R psi = psi_of<R>(rho);
+    const R psi = psi_of<R>(rho, P.psi_form);
     const Macro<R> m = node_macro<R>(f, g, rho, E, psi, gpx, gpy, gpz, gEx, gEy, gEz, grx, gry,
                                      grz, P);
     const R ir = R(1) / rho;
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const double* __restrict__ st
     GEbz -= Fbz;
     const R Grbx = P.T_lat * Fbx, Grby = P.T_lat * Fby, Grbz = P.T_lat * Fbz;
     rb -= P.gravity * Fbz;
-    rb += psib * psi * ir * ir;   // psi = exp(-1/rho)
+    rb += P.psi_form ? psib * (R(1) - psi) : psib * psi * ir * ir;   // d psi / d rho
 
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
@@ -1016,8 +1016,8 @@ __global__ __launch_bounds__(256) void k_adj_stencil(const R* __restrict__ srho,
       }
     }
     const R rho = srho[n];
-    const R psi = psi_of<R>(rho);
-    const double addf = (double)(qb + pb * psi / (rho * rho));
+    const R psi = psi_of<R>(rho, P.psi_form);
+    const double addf = (double)(qb + (P.psi_form ? pb * (R(1) - psi) : pb * psi / (rho * rho)));
     const double addg = (double)eb;
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
@@ -1124,6 +1124,7 @@ int validate(const lbm_params* p) {
   if (!isfinite(p->gravity)) return fail(LBM_EINVAL, "gravity must be finite");
   if (!isfinite(p->rho_wall_d) || !isfinite(p->rho_wall_u))
     return fail(LBM_EINVAL, "wall densities must be finite");
+  if (p->psi_form != 0 && p->psi_form != 1) return fail(LBM_EINVAL, "psi_form must be 0 or 1");
   if (p->storage >= LBM_FP16DEV && (!(p->rho_ref > 0.0) || !(p->T_ref > 0.0)))
     return fail(LBM_EINVAL, "16-bit storage needs rho_ref > 0 and T_ref > 0");
   return LBM_OK;
@@ -1192,8 +1193,10 @@ DevParams<R> dev_params(const lbm_params& p) {
   d.T_lat = (R)T_lat;
   d.wet_d = p.rho_wall_d > 0.0 ? 1 : 0;
   d.wet_u = p.rho_wall_u > 0.0 ? 1 : 0;
-  d.psi_wd = (R)(d.wet_d ? exp(-1.0 / p.rho_wall_d) : 0.0);
-  d.psi_wu = (R)(d.wet_u ? exp(-1.0 / p.rho_wall_u) : 0.0);
+  d.psi_form = p.psi_form;
+  auto psi_host = [&](double r) { return p.psi_form ? 1.0 - exp(-r) : exp(-1.0 / r); };
+  d.psi_wd = (R)(d.wet_d ? psi_host(p.rho_wall_d) : 0.0);
+  d.psi_wu = (R)(d.wet_u ? psi_host(p.rho_wall_u) : 0.0);
   const bool dev = p.storage >= LBM_FP16DEV;
   for (int l = 0; l < Q; ++l) {
     // reference populations: equilibrium at rest of (rho_ref, T_ref)

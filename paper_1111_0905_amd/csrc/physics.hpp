@@ -67,6 +67,7 @@ struct DevParams {
   // (prescribed wall density); otherwise the mirror image of the wall plane
   int wet_d, wet_u;
   R psi_wd, psi_wu;
+  int psi_form;         // 0: exp(-1/rho); 1: 1 - exp(-rho)
 };
 
 // ----------------------------------------------------------- storage codecs
@@ -249,7 +250,11 @@ __device__ __forceinline__ void store_moving(typename C::S* b, int l, size_t N, 
 // ----------------------------------------------------------- node arithmetic
 
 template <typename R>
-__device__ __forceinline__ R psi_of(R rho) { return exp(R(-1) / rho); }
+__device__ __forceinline__ R psi_of(R rho, int form) {
+  // one exponential for either form (form is uniform over the launch)
+  const R e = exp(form ? -rho : R(-1) / rho);
+  return form ? R(1) - e : e;
+}
 
 // W-stencil central gradient sum_l W_l c_l a(x + c_l); at(l) returns the
 // neighbour value in direction l.

@@ -40,6 +40,7 @@ class _CParams(ctypes.Structure):
         ("c_v", ctypes.c_double), ("rho_kappa", ctypes.c_double),
         ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("T_lat", ctypes.c_double),
         ("rho_wall_d", ctypes.c_double), ("rho_wall_u", ctypes.c_double),
+        ("psi_form", ctypes.c_int32),
     ]
 
 
@@ -69,6 +70,7 @@ class Params:
     T_lat: float = 0.0
     rho_wall_d: float = 0.0
     rho_wall_u: float = 0.0
+    psi_form: int = 0
 
     def c(self) -> _CParams:
         return _CParams(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -50,7 +50,8 @@ def test_workspace_bytes_and_validation(lib):
     assert lbm.lbm_workspace_bytes(p16) < nb
     for bad in [dict(nx=0), dict(tau_nu=0.5), dict(tau_kappa=0.3), dict(G=0.1), dict(T_d=0.0),
                 dict(nz=1), dict(storage=7), dict(kernel=9), dict(c_v=0.0), dict(tile_y=3),
-                dict(storage=lbm.LBM_FP16DEV, rho_ref=0.0)]:
+                dict(storage=lbm.LBM_FP16DEV, rho_ref=0.0), dict(psi_form=2),
+                dict(rho_wall_d=float("nan"))]:
         q = lbm.Params(8, 8, 8)
         for k, v in bad.items():
             setattr(q, k, v)

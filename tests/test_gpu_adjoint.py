@@ -109,6 +109,35 @@ def test_one_step_adjoint_with_wetting_walls(glbm):
     assert abs(grads[1] - dTd.item()) < 1e-11 * max(1.0, abs(dTd.item()))
 
 
+def test_one_step_adjoint_with_sc_pseudopotential(glbm):
+    # psi = 1 - exp(-rho): d psi / d rho = exp(-rho) in the local and the
+    # stencil parts of the adjoint
+    nx, ny, nz = 6, 5, 7
+    print("case: one-step adjoint, Shan-Chen psi", flush=True)
+    kw = _kw(G=-4 * TC, psi_form=1, rho_wall_u=0.4)
+    p_o = olbm.Params(nx, ny, nz, **kw)
+    rho0 = synth.noisy_density(nx, ny, nz, 1.0, 0.05, 29)
+    f, g = olbm.init_state(p_o, torch.from_numpy(rho0))
+    for _ in range(3):
+        f, g = olbm.step(p_o, f, g)
+    s = torch.cat([f, g]).detach()
+    lam = torch.from_numpy(np.random.default_rng(8).standard_normal(s.shape))
+    s_r = s.clone().requires_grad_(True)
+    Gt = torch.tensor(kw["G"], dtype=torch.float64, requires_grad=True)
+    Tdt = torch.tensor(kw["T_d"], dtype=torch.float64, requires_grad=True)
+    fo, go = olbm.step(p_o, s_r[:19], s_r[19:], G=Gt, T_d=Tdt)
+    ds, dG, dTd = torch.autograd.grad(torch.cat([fo, go]), [s_r, Gt, Tdt], grad_outputs=lam)
+    p_g = glbm.Params(nx, ny, nz, storage=glbm.LBM_FP64, adjoint=1, **kw)
+    lat = glbm.Lattice(p_g, torch.from_numpy(rho0).cuda())
+    lam_g = lam.cuda().contiguous()
+    out_g = torch.empty_like(lam_g)
+    grads = np.zeros(2)
+    glbm.lbm_adjoint_step(lat.h, s.cuda().contiguous(), lam_g, out_g, grads)
+    assert _rel(out_g.cpu().numpy(), ds.numpy()) < 1e-11
+    assert abs(grads[0] - dG.item()) < 1e-11 * max(1.0, abs(dG.item()))
+    assert abs(grads[1] - dTd.item()) < 1e-11 * max(1.0, abs(dTd.item()))
+
+
 def test_qbot_and_its_adjoint(glbm):
     nx, ny, nz = 7, 6, 5
     kw = _kw()
