@@ -74,7 +74,9 @@ enum {
 enum {
   LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step (default): with tile_x = tile_y = 0
                                   the library picks the tile and whether the next plane stays in
-                                  registers from the storage type; with an explicit tile it does */
+                                  registers from the storage type (FP64 64 x 2 and FP32 32 x 16 in
+                                  registers, the 16-bit forms 64 x 16 re-read); with an explicit
+                                  tile of at most 512 threads it keeps the plane in registers */
   LBM_KERNEL_REFERENCE = 1,    /* two plain kernels per step (moments, then collide+stream) */
   LBM_KERNEL_FUSED_RELOAD = 2  /* one z-marching kernel per step, populations re-read from cache */
 };
@@ -92,7 +94,8 @@ enum {
  *   tau_nu, tau_kappa > 1/2: relaxation times of f and g;
  *     nu = (tau_nu - 1/2)/3, kappa = c_v (tau_kappa - 1/2) rho_kappa / 3.
  *   G: strength of eq. (FORCE), G < 0 (attraction); critical point
- *     rho_c = 1, T_c = -G / e^2, bulk pressure rho T + (G/2) exp(-2/rho).
+ *     rho_c = 1, T_c = -G / e^2, bulk pressure rho T + (G/2) exp(-2/rho)
+ *     (with psi_form = 1: rho_c = ln 2, T_c = -G / 4, rho T + (G/2) psi^2).
  *   T_d, T_u > 0: bottom and top wall temperatures.
  *   gravity >= 0: body force rho * (0, 0, -gravity).
  *   c_v > 0: specific heat at constant volume.
@@ -103,6 +106,7 @@ enum {
  *   rho_ref, T_ref: reference state of the FP16/BF16 deviation storage
  *     (pop_ref = equilibrium at rest of (rho_ref, T_ref)); ignored otherwise.
  *   periodic_z: 0 = walls (nz >= 2), 1 = periodic in z as well.
+ *   rho_wall_d, rho_wall_u, psi_form: see the fields below.
  *   kernel: LBM_KERNEL_*.
  *   tile_x x tile_y: x-y tile of one fused-kernel work-group; supported
  *     64 x {1, 2, 4, 8, 16} and 32 x {8, 16, 32}; 0 picks the default.
