@@ -120,7 +120,8 @@ typedef struct lbm_params {
   int32_t tile_y;      /* fused-kernel tile height: 0 (default), 1..32, see lbm_init */
   int32_t z_chunk;     /* planes per fused-kernel work-group column; 0 = the whole
                           height, split into chunks of at least 4 planes when
-                          the lattice is too small to give about 16 waves per CU */
+                          the lattice has fewer tiles than the GPU holds work-groups
+                          of this kernel at once (the runtime's occupancy) */
   int32_t adjoint;     /* 1 = reserve workspace for the lbm_adjoint_* entry points */
   double tau_nu, tau_kappa;
   double G;

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -1230,27 +1231,52 @@ int launch_tile(lbm_handle* h, const void* in, void* out) {
   return LBM_OK;
 }
 
-// Tile shapes (TX x TY) the library is built for.  Keeping the next plane in
-// registers is only built for tiles of at most 512 threads.
-template <typename C, bool KEEP>
-int launch_fused(lbm_handle* h, const void* in, void* out) {
-  const int tx = h->tile_x, ty = h->tile_y;
+// Tile shapes (TX x TY) the library is built for: f(TX, TY, KEEP) is called
+// with the shape as integral constants.  Keeping the next plane in registers
+// is only built for tiles of at most 512 threads.
+template <bool KEEP, typename F>
+int with_tile(int tx, int ty, F&& f) {
+  using std::bool_constant;
+  using std::integral_constant;
+  using I64 = integral_constant<int, 64>;
+  using I32 = integral_constant<int, 32>;
   if (tx == 64) {
     switch (ty) {
-      case 1: return launch_tile<C, 64, 1, KEEP>(h, in, out);
-      case 2: return launch_tile<C, 64, 2, KEEP>(h, in, out);
-      case 4: return launch_tile<C, 64, 4, KEEP>(h, in, out);
-      case 8: return launch_tile<C, 64, 8, KEEP>(h, in, out);
-      case 16: return launch_tile<C, 64, 16, false>(h, in, out);
+      case 1: return f(I64{}, integral_constant<int, 1>{}, bool_constant<KEEP>{});
+      case 2: return f(I64{}, integral_constant<int, 2>{}, bool_constant<KEEP>{});
+      case 4: return f(I64{}, integral_constant<int, 4>{}, bool_constant<KEEP>{});
+      case 8: return f(I64{}, integral_constant<int, 8>{}, bool_constant<KEEP>{});
+      case 16: return f(I64{}, integral_constant<int, 16>{}, bool_constant<false>{});
     }
   } else if (tx == 32) {
     switch (ty) {
-      case 8: return launch_tile<C, 32, 8, KEEP>(h, in, out);
-      case 16: return launch_tile<C, 32, 16, KEEP>(h, in, out);
-      case 32: return launch_tile<C, 32, 32, false>(h, in, out);
+      case 8: return f(I32{}, integral_constant<int, 8>{}, bool_constant<KEEP>{});
+      case 16: return f(I32{}, integral_constant<int, 16>{}, bool_constant<KEEP>{});
+      case 32: return f(I32{}, integral_constant<int, 32>{}, bool_constant<false>{});
     }
   }
   return fail(LBM_EINVAL, "unsupported tile shape");
+}
+
+template <typename C, bool KEEP>
+int launch_fused(lbm_handle* h, const void* in, void* out) {
+  return with_tile<KEEP>(h->tile_x, h->tile_y, [&](auto X, auto Y, auto K) {
+    return launch_tile<C, decltype(X)::value, decltype(Y)::value, decltype(K)::value>(h, in, out);
+  });
+}
+
+// Work-groups of the fused kernel for this tile that one compute unit holds
+// at once (registers and LDS decide), or <= 0 if the runtime cannot tell.
+template <typename C, bool KEEP>
+int fused_groups_per_cu(int tx, int ty) {
+  return with_tile<KEEP>(tx, ty, [&](auto X, auto Y, auto K) {
+    constexpr int TX = decltype(X)::value, TY = decltype(Y)::value;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<C, TX, TY, decltype(K)::value>,
+                                                     TX * TY, 0) != hipSuccess)
+      return 0;
+    return nb;
+  });
 }
 
 template <typename C>
@@ -1506,6 +1532,12 @@ int dispatch(int storage, A... a) {
   }
 }
 template <typename C> struct StepFn { static int run(lbm_handle* h) { return do_step<C>(h); } };
+template <typename C> struct OccupancyFn {
+  static int run(int kernel, int tx, int ty) {
+    return kernel == LBM_KERNEL_FUSED_RELOAD ? fused_groups_per_cu<C, false>(tx, ty)
+                                             : fused_groups_per_cu<C, true>(tx, ty);
+  }
+};
 template <typename C> struct InitFn {
   static int run(lbm_handle* h, const double* r, const double* T) { return do_init<C>(h, r, T); }
 };
@@ -1613,14 +1645,24 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   if (p->z_chunk) {
     h->z_chunk = std::min(p->z_chunk, p->nz);
   } else {
-    // split the z columns until the launch holds about 16 waves per compute
-    // unit (256 CUs); every chunk re-reads one halo plane on each side, so
-    // chunks stay at least 4 planes deep
+    // split the z columns until the launch has as many work-groups as the
+    // GPU holds at once (compute units x work-groups per unit for this
+    // kernel), so that one wave of work-groups covers the lattice; every
+    // chunk re-reads one halo plane on each side, so chunks stay at least 4
+    // planes deep
     const long long tiles = (long long)((p->nx + h->tile_x - 1) / h->tile_x) *
                             ((p->ny + h->tile_y - 1) / h->tile_y);
-    const long long waves = tiles * ((h->tile_x * h->tile_y + 63) / 64);
-    const long long want = 16LL * 256;
-    const long long nzc = std::max(1LL, (want + waves - 1) / waves);
+    int per_cu = h->kernel == LBM_KERNEL_REFERENCE
+                     ? 1
+                     : dispatch<OccupancyFn>(p->storage, h->kernel, h->tile_x, h->tile_y);
+    if (per_cu < 1) per_cu = 1;
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    const long long want = (long long)cus * per_cu;
+    const long long nzc = std::max(1LL, (want + tiles - 1) / tiles);
     int zc = (int)((p->nz + nzc - 1) / nzc);
     zc = std::max(zc, 4);
     h->z_chunk = std::min(zc, p->nz);
