@@ -74,8 +74,9 @@ enum {
 enum {
   LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step (default): with tile_x = tile_y = 0
                                   the library picks the tile and whether the next plane stays in
-                                  registers from the storage type (FP64 64 x 2 and FP32 32 x 16 in
-                                  registers, the 16-bit forms 64 x 16 re-read); with an explicit
+                                  registers from the storage type and the plane size (FP64 64 x 2
+                                  and FP32 32 x 16, or 64 x 8 for planes under 512^2 nodes, in
+                                  registers; the 16-bit forms 64 x 16 re-read); with an explicit
                                   tile of at most 512 threads it keeps the plane in registers */
   LBM_KERNEL_REFERENCE = 1,    /* two plain kernels per step (moments, then collide+stream) */
   LBM_KERNEL_FUSED_RELOAD = 2  /* one z-marching kernel per step, populations re-read from cache */

@@ -1622,17 +1622,25 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->aE = L.adj ? h->gbar + 10 * L.N : nullptr;
   h->cur = 0;
   h->t = 0;
-  // defaults from tile/variant sweeps at 512^3 on MI355X: FP32 keeps the next
-  // plane in registers on 32 x 16 tiles; the 16-bit forms re-read it from
-  // cache on 64 x 16 tiles
+  // defaults from tile/variant sweeps on MI355X: FP32 keeps the next plane in
+  // registers, on 32 x 16 tiles when a plane holds at least two of them per
+  // compute unit (512^3: 2-3 % faster than 64 x 8) and on 64 x 8 tiles below
+  // that (256^3: 6 %, 128^3: 11 % faster than 32 x 16); the 16-bit forms
+  // re-read it from cache on 64 x 16 tiles
+  int cus = 0, dev = 0;  // compute units of the current device
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
   h->kernel = p->kernel;
   if (p->tile_x == 0 && p->tile_y == 0) {
     if (p->storage == LBM_FP64) {
       h->tile_x = 64;
       h->tile_y = 2;
     } else if (p->storage == LBM_FP32) {
-      h->tile_x = 32;
-      h->tile_y = 16;
+      const bool wide = (long long)p->nx * p->ny >= 2LL * cus * 32 * 16;
+      h->tile_x = wide ? 32 : 64;
+      h->tile_y = wide ? 16 : 8;
     } else {
       h->tile_x = 64;
       h->tile_y = 16;
@@ -1656,11 +1664,6 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
                      ? 1
                      : dispatch<OccupancyFn>(p->storage, h->kernel, h->tile_x, h->tile_y);
     if (per_cu < 1) per_cu = 1;
-    int cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus < 1)
-      cus = 256;
     const long long want = (long long)cus * per_cu;
     const long long nzc = std::max(1LL, (want + tiles - 1) / tiles);
     int zc = (int)((p->nz + nzc - 1) / nzc);
