@@ -82,3 +82,14 @@ def bubbly_density(n: int, rho_g: float, rho_l: float, n_bubbles: int, r_min: fl
         prof = rho_g + (rho_l - rho_g) * 0.5 * (1.0 + np.tanh((np.sqrt(d2) - R) / width))
         out = np.minimum(out, prof)
     return out
+
+
+def noisy_density_at(nx: int, ny: int, nz: int, rho_mean: float, noise_amp: float, seed: int,
+                     k: np.ndarray, j: np.ndarray, i: np.ndarray) -> np.ndarray:
+    """noisy_density(nx, ny, nz, ...)[k, j, i] for broadcastable index arrays,
+    without generating the whole field (same counters, same values)."""
+    k, j, i = np.broadcast_arrays(np.asarray(k, dtype=np.uint64), np.asarray(j, dtype=np.uint64),
+                                  np.asarray(i, dtype=np.uint64))
+    c = i + np.uint64(nx) * (j + np.uint64(ny) * k)
+    u = (splitmix64(seed, c) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return rho_mean * (1.0 + noise_amp * (2.0 * u - 1.0))
