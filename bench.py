@@ -108,14 +108,14 @@ def measured_traffic(storage, n):
     return d["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(seconds=15.0):
-    """FP64 oracle on the host, 64^3 sample of the same physics."""
+def cpu_baseline(seconds=15.0, n=64, max_steps=None):
+    """FP64 oracle on the host, n^3 sample of the same physics, stepped for
+    about `seconds` (or max_steps) after one warm-up step."""
     import torch
     from oracle import lbm as olbm
     threads = os.cpu_count() or 1
     torch.set_num_threads(threads)
     from paper_1111_0905_amd import lbm
-    n = 64
     w = workload_params(lbm, 512, "fp32")      # physics of the full-size cell
     p = olbm.Params(n, n, n, tau_nu=w.tau_nu, tau_kappa=w.tau_kappa, G=w.G, T_d=w.T_d,
                     T_u=w.T_u, gravity=w.gravity, c_v=w.c_v, rho_kappa=w.rho_kappa,
@@ -124,7 +124,7 @@ def cpu_baseline(seconds=15.0):
     o.step(1)
     steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
+    while (time.perf_counter() - t0 < seconds) if max_steps is None else (steps < max_steps):
         o.step(1)
         steps += 1
     dt = time.perf_counter() - t0
@@ -148,7 +148,15 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time kernel/tile variants")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 CPU oracle at 32^3, 64^3 (100 steps) and 128^3 "
+                         "(20 steps), one JSON line each")
     args = ap.parse_args()
+
+    if args.oracle_timing:
+        for n, steps in ((32, 100), (64, 100), (128, 20)):
+            print(json.dumps(cpu_baseline(n=n, max_steps=steps)), flush=True)
+        return
 
     if args.copy_probe:
         import torch
