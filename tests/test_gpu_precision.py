@@ -6,7 +6,7 @@ in FP32; FP32 storage is the baseline.  Three comparisons, each printing the
 errors it measures:
 
 * a 64^3 crop of the boiling convection cell (the 512^3 cell's physics on a
-  64^3 box: T_c = 0.12, nu = 0.0165, Pr = 9, gravity from Ra = 1e7 at L = 512),
+  64^3 box: T_c = 0.08, nu = 0.0165, Pr = 9, gravity from Ra = 1e7 at L = 512),
   100 steps from the seeded field: moment fields, Nu_bot, Nu_top and Nu(z);
 * coexistence densities of a flat interface (periodic 1 x 1 x 96 column,
   0.8 T_c, 3000 steps);
