@@ -32,10 +32,10 @@ RA = 1e7                               # Rayleigh number of the boiling cell (Ta
 
 
 def workload_params(lbm, n, storage, kernel=0, tile_y=0, z_chunk=0, tile_x=0):
-    """The boiling convection cell of side n: T_c = 0.12, T_d = 0.95 T_c,
+    """The boiling convection cell of side n: T_c = 0.08, T_d = 0.95 T_c,
     T_u = 0.85 T_c, nu = 0.0165, Pr = 9 in the liquid, gravity from Ra, mean
-    density from the hydrostatic liquid column (bottom layer past the liquid
-    spinodal)."""
+    density 0.12 below that of the hydrostatic liquid column whose bottom
+    layer sits on the liquid spinodal."""
     from paper_1111_0905_amd import experiments
     rho = experiments.boiling_density(n, RA)
     return experiments.cell_params(n, rho, RA, storage, kernel=kernel, tile_x=tile_x,
