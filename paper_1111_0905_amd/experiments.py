@@ -60,11 +60,14 @@ def boiling_density(n, Ra, T_c=TC, margin=BOIL_MARGIN, **kw):
     """Mean density of the boiling cell: `margin` below the mean density of
     the hydrostatic liquid column whose bottom layer sits on the liquid
     spinodal.  Once convection mixes the bulk, the bottom layer of a cell only
-    slightly past that threshold stays liquid (at 128^3, Ra ~ 1e6, margins
-    0.045 and 0.1 formed no vapour within 10^4 steps); at 0.12 a vapour film
-    forms on the bottom wall and breaks up into rising bubbles within 3 x 10^4
-    steps; at 0.16 and above the film persists.  Gravity depends on the
-    density through Ra, so the two are iterated to a fixed point."""
+    slightly past that threshold stays liquid (with T_c = 0.12 at 128^3,
+    Ra ~ 1e6, margins 0.045 and 0.1 formed no vapour within 10^4 steps; at
+    0.12 a vapour film formed on the bottom wall and broke up into rising
+    bubbles within 3 x 10^4 steps; from 0.16 on the film persisted).  With the
+    cell's T_c = 0.08 and margin 0.12 a film forms within about 1.2 x 10^4
+    steps at 128^3 and feeds 4-7 rising bubbles in the statistically steady
+    state.  Gravity depends on the density through Ra, so the two are
+    iterated to a fixed point."""
     G = thermo.coupling_for_tc(T_c)
     rho = 1.975 - margin
     for _ in range(20):
