@@ -104,7 +104,12 @@ TC = 0.05
 G = eos.coupling_for_tc(TC)
 # after 3000 steps the interface is still relaxing (densities about 1 % from
 # the Maxwell values), so the bars are on agreement with the oracle's state
-# at that time, which the slow relaxation makes sensitive to rounding
+# at that time, which the slow relaxation makes sensitive to rounding.  The
+# 16-bit bars are a few units of the storage's relative rounding of the
+# deviations, which on the vapour side are of the order of the populations
+# themselves: FP16 keeps 11 significant bits (u = 2^-11 ~ 4.9e-4; bar ~ 6 u),
+# BF16 8 (u = 2^-8 ~ 3.9e-3; bar ~ 2.5 u); the FP32 rest pair adds the
+# rounding of one FP32 add per node and step
 SLAB_BARS = {"fp32": 2e-5, "fp16dev": 3e-3, "bf16dev": 1e-2}
 
 
@@ -151,6 +156,12 @@ def test_coexistence_densities(glbm, slab, storage):
 
 BUB_N = 32
 BUB_STEPS = 600
+# relative change of the total mass over the run.  The rest pair (FP32 in
+# every non-FP64 form) takes one FP32 add per node and step; unbiased
+# roundings of unit 6e-8 random-walk to about 6e-8 sqrt(steps / nodes)
+# ~ 8e-9 of the total, the 16-bit bar sits below that (their remainder form
+# also returns the store residuals); FP32 storage additionally leaves the
+# rounding of its collided moving values uncompensated
 MASS_BARS = {"fp32": 1e-7, "fp16dev": 1e-9, "bf16dev": 1e-9}
 
 
