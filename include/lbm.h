@@ -72,14 +72,18 @@ enum {
 
 /* which implementation of the step */
 enum {
-  LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step (default): with tile_x = tile_y = 0
-                                  the library picks the tile and whether the next plane stays in
-                                  registers from the storage type and the plane size (FP64 64 x 2
-                                  and FP32 32 x 16, or 64 x 8 for planes under 512^2 nodes, in
-                                  registers; the 16-bit forms 64 x 16 re-read); with an explicit
-                                  tile of at most 512 threads it keeps the plane in registers */
+  LBM_KERNEL_FUSED = 0,        /* one z-marching kernel per step (default).  With tile_x = tile_y = 0
+                                  the library picks: FP32 and the 16-bit forms the pipelined kernel
+                                  (LBM_KERNEL_PIPELINED) on 512-thread tiles 128 x 4 (nx >= 128),
+                                  64 x 8 (nx >= 64) or 32 x 16; FP64 the register-resident kernel on
+                                  64 x 2 tiles.  With an explicit tile (of at most 512 threads) it is
+                                  the register-resident kernel on that tile */
   LBM_KERNEL_REFERENCE = 1,    /* two plain kernels per step (moments, then collide+stream) */
-  LBM_KERNEL_FUSED_RELOAD = 2  /* one z-marching kernel per step, populations re-read from cache */
+  LBM_KERNEL_FUSED_RELOAD = 2, /* one z-marching kernel per step, populations re-read from cache */
+  LBM_KERNEL_PIPELINED = 3     /* one z-marching kernel per step with the loads of plane k+2 in
+                                  flight while plane k collides (FP32 and 16-bit storage only;
+                                  tiles 128 x 4, 64 x 8, 32 x 16, 32 x 8, 16 x 16; 0 x 0 picks
+                                  the widest 512-thread tile the plane fills) */
 };
 
 enum {
@@ -109,8 +113,9 @@ enum {
  *   periodic_z: 0 = walls (nz >= 2), 1 = periodic in z as well.
  *   rho_wall_d, rho_wall_u, psi_form: see the fields below.
  *   kernel: LBM_KERNEL_*.
- *   tile_x x tile_y: x-y tile of one fused-kernel work-group; supported
- *     64 x {1, 2, 4, 8, 16} and 32 x {8, 16, 32}; 0 picks the default.
+ *   tile_x x tile_y: x-y tile of one z-marching work-group; supported
+ *     64 x {1, 2, 4, 8, 16} and 32 x {8, 16, 32} (fused kernels), 128 x 4,
+ *     64 x 8, 32 x 16, 32 x 8 and 16 x 16 (pipelined); 0 picks the default.
  */
 typedef struct lbm_params {
   int32_t nx, ny, nz;

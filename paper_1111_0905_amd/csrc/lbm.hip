@@ -476,6 +476,10 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
   }
 }
 
+// ---------------------------------------------------------------- pipelined path
+
+#include "pipe.hpp"
+
 // ---------------------------------------------------------------- diagnostics
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -1107,9 +1111,16 @@ int validate(const lbm_params* p) {
     return fail(LBM_EINVAL, "lattice too large (one direction's population array must stay below 4 GiB)");
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16DEV) return fail(LBM_EINVAL, "unknown storage");
   if (p->kernel != LBM_KERNEL_FUSED && p->kernel != LBM_KERNEL_REFERENCE &&
-      p->kernel != LBM_KERNEL_FUSED_RELOAD)
+      p->kernel != LBM_KERNEL_FUSED_RELOAD && p->kernel != LBM_KERNEL_PIPELINED)
     return fail(LBM_EINVAL, "unknown kernel");
-  {
+  if (p->kernel == LBM_KERNEL_PIPELINED) {
+    if (p->storage == LBM_FP64)
+      return fail(LBM_EINVAL, "the pipelined kernel is built for FP32 and the 16-bit forms only");
+    const int tx = p->tile_x, ty = p->tile_y;
+    const bool ok = (tx == 0 && ty == 0) || (tx == 32 && (ty == 8 || ty == 16)) ||
+                    (tx == 64 && ty == 8) || (tx == 16 && ty == 16) || (tx == 128 && ty == 4);
+    if (!ok) return fail(LBM_EINVAL, "unsupported tile shape (tile_x, tile_y) for the pipelined kernel");
+  } else {
     const int tx = p->tile_x, ty = p->tile_y;
     const bool ok = (tx == 0 && ty == 0) ||
                     (tx == 64 && (ty == 1 || ty == 2 || ty == 4 || ty == 8 || ty == 16)) ||
@@ -1279,6 +1290,95 @@ int fused_groups_per_cu(int tx, int ty) {
   });
 }
 
+pipe::PParams pipe_params(const lbm_params& p) {
+  pipe::PParams d;
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  d.periodic_z = p.periodic_z ? 1 : 0;
+  d.omega_f = (float)(1.0 / p.tau_nu);
+  d.omega_g = (float)(1.0 / p.tau_kappa);
+  d.tau_nu = (float)p.tau_nu;
+  d.G = (float)p.G;
+  d.gravity = (float)p.gravity;
+  d.inv_cv = (float)(1.0 / p.c_v);
+  d.gamma = (float)(1.0 + 1.0 / p.c_v);
+  d.rho_kappa = (float)p.rho_kappa;
+  d.T_d = (float)p.T_d;
+  d.T_u = (float)p.T_u;
+  const double T_lat = p.T_lat > 0.0 ? p.T_lat : 0.5 * (p.T_d + p.T_u);
+  d.T_lat = (float)T_lat;
+  const bool dev = p.storage >= LBM_FP16DEV;
+  d.rho_ref0 = dev ? (float)p.rho_ref : 0.f;
+  d.T_ref0 = dev ? (float)p.T_ref : 0.f;
+  // sums of the FP32 reference populations of the moving directions (the
+  // values the 16-bit words are deviations from; the same as dev_params)
+  double sf = 0.0, sg = 0.0;
+  for (int l = 1; l < Q; ++l) {
+    const double w = wlat<double>(l);
+    sf += (double)(float)(w * p.rho_ref + af<double>(l) * p.rho_ref * (T_lat - 1.0 / 3.0));
+    sg += (double)(float)(w * p.rho_ref * p.T_ref + bg<double>(l) * (p.rho_kappa - p.rho_ref) * p.T_ref);
+  }
+  d.Fref = dev ? (float)sf : 0.f;
+  d.Gref = dev ? (float)sg : 0.f;
+  d.wet_d = p.rho_wall_d > 0.0 ? 1 : 0;
+  d.wet_u = p.rho_wall_u > 0.0 ? 1 : 0;
+  d.psi_form = p.psi_form;
+  auto psi_host = [&](double r) { return p.psi_form ? 1.0 - exp(-r) : exp(-1.0 / r); };
+  d.psi_wd = d.wet_d ? (float)psi_host(p.rho_wall_d) : 0.f;
+  d.psi_wu = d.wet_u ? (float)psi_host(p.rho_wall_u) : 0.f;
+  return d;
+}
+
+// Tile shapes of the pipelined kernel: f(TX, TY) with integral constants.
+template <typename F>
+int with_pipe_tile(int tx, int ty, F&& f) {
+  using std::integral_constant;
+  if (tx == 32 && ty == 16) return f(integral_constant<int, 32>{}, integral_constant<int, 16>{});
+  if (tx == 32 && ty == 8) return f(integral_constant<int, 32>{}, integral_constant<int, 8>{});
+  if (tx == 64 && ty == 8) return f(integral_constant<int, 64>{}, integral_constant<int, 8>{});
+  if (tx == 16 && ty == 16) return f(integral_constant<int, 16>{}, integral_constant<int, 16>{});
+  if (tx == 128 && ty == 4) return f(integral_constant<int, 128>{}, integral_constant<int, 4>{});
+  return fail(LBM_EINVAL, "unsupported tile shape for the pipelined kernel");
+}
+
+template <typename C>
+int launch_pipe(lbm_handle* h, const void* in, void* out) {
+  if constexpr (std::is_same<C, F64>::value) {
+    return fail(LBM_EINVAL, "the pipelined kernel is built for FP32 and the 16-bit forms only");
+  } else {
+    const pipe::PParams P = pipe_params(h->p);
+    return with_pipe_tile(h->tile_x, h->tile_y, [&](auto X, auto Y) -> int {
+      constexpr int TX = decltype(X)::value, TY = decltype(Y)::value;
+      const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
+      const int kz = h->z_chunk;
+      const int nzc = (h->p.nz + kz - 1) / kz;
+      const long long nblk = (long long)ntx * nty * nzc;
+      if (nblk > 0x7fffffffLL) return fail(LBM_EINVAL, "grid too large");
+      hipLaunchKernelGGL((pipe::k_pipe<C, TX, TY>), dim3((unsigned)nblk), dim3(TX * TY), 0,
+                         h->stream, (const char*)in, (char*)out, P, ntx, nty, kz);
+      HIP_TRY(hipGetLastError());
+      return (int)LBM_OK;
+    });
+  }
+}
+
+template <typename C>
+int pipe_groups_per_cu(int tx, int ty) {
+  if constexpr (std::is_same<C, F64>::value) {
+    return 0;
+  } else {
+    return with_pipe_tile(tx, ty, [&](auto X, auto Y) -> int {
+      constexpr int TX = decltype(X)::value, TY = decltype(Y)::value;
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pipe::k_pipe<C, TX, TY>, TX * TY, 0) !=
+          hipSuccess)
+        return 0;
+      return nb;
+    });
+  }
+}
+
 template <typename C>
 int launch_rhoE(lbm_handle* h, const void* in) {
   using R = typename C::R;
@@ -1310,6 +1410,7 @@ int do_step(lbm_handle* h) {
   switch (h->kernel) {
     case LBM_KERNEL_FUSED: rc = launch_fused<C, true>(h, in, out); break;
     case LBM_KERNEL_FUSED_RELOAD: rc = launch_fused<C, false>(h, in, out); break;
+    case LBM_KERNEL_PIPELINED: rc = launch_pipe<C>(h, in, out); break;
     default: rc = launch_reference<C>(h, in, out); break;
   }
   if (rc) return rc;
@@ -1534,6 +1635,7 @@ int dispatch(int storage, A... a) {
 template <typename C> struct StepFn { static int run(lbm_handle* h) { return do_step<C>(h); } };
 template <typename C> struct OccupancyFn {
   static int run(int kernel, int tx, int ty) {
+    if (kernel == LBM_KERNEL_PIPELINED) return pipe_groups_per_cu<C>(tx, ty);
     return kernel == LBM_KERNEL_FUSED_RELOAD ? fused_groups_per_cu<C, false>(tx, ty)
                                              : fused_groups_per_cu<C, true>(tx, ty);
   }
@@ -1622,21 +1724,32 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->aE = L.adj ? h->gbar + 10 * L.N : nullptr;
   h->cur = 0;
   h->t = 0;
-  // defaults from tile/variant sweeps on MI355X: FP32 keeps the next plane in
-  // registers, on 32 x 16 tiles when a plane holds at least two of them per
-  // compute unit (512^3: 2-3 % faster than 64 x 8) and on 64 x 8 tiles below
-  // that (256^3: 6 %, 128^3: 11 % faster than 32 x 16); the 16-bit forms
-  // re-read it from cache on 64 x 16 tiles
+  // defaults from tile/variant sweeps on MI355X (same process, alternating):
+  // FP32 and the 16-bit forms use the pipelined kernel on 512-thread tiles
+  // as wide as the plane allows (128 x 4: 512^3 FP32 9.14 ms, 256^3 -10 %,
+  // 128^3 -12 % against the register-resident kernel on 32 x 16 / 64 x 8;
+  // FP16 512^3 5.59 ms against 6.74 ms re-reading on 64 x 16; wider rows
+  // mean fewer cache lines shared with the x-neighbour tiles and fewer
+  // scattered side-ring loads); FP64 keeps the register-resident kernel on
+  // 64 x 2 tiles
   int cus = 0, dev = 0;  // compute units of the current device
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
   h->kernel = p->kernel;
-  if (p->tile_x == 0 && p->tile_y == 0) {
+  const int wide_x = p->nx >= 128 ? 128 : (p->nx >= 64 ? 64 : 32);
+  if (p->kernel == LBM_KERNEL_PIPELINED) {
+    h->tile_x = p->tile_x ? p->tile_x : wide_x;
+    h->tile_y = p->tile_y ? p->tile_y : 512 / h->tile_x;
+  } else if (p->tile_x == 0 && p->tile_y == 0) {
     if (p->storage == LBM_FP64) {
       h->tile_x = 64;
       h->tile_y = 2;
+    } else if (p->kernel == LBM_KERNEL_FUSED) {
+      h->kernel = LBM_KERNEL_PIPELINED;
+      h->tile_x = wide_x;
+      h->tile_y = 512 / wide_x;
     } else if (p->storage == LBM_FP32) {
       const bool wide = (long long)p->nx * p->ny >= 2LL * cus * 32 * 16;
       h->tile_x = wide ? 32 : 64;
@@ -1644,7 +1757,6 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
     } else {
       h->tile_x = 64;
       h->tile_y = 16;
-      if (p->kernel == LBM_KERNEL_FUSED) h->kernel = LBM_KERNEL_FUSED_RELOAD;
     }
   } else {
     h->tile_x = p->tile_x ? p->tile_x : 64;

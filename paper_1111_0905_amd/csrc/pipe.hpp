@@ -1,0 +1,446 @@
+// pipe.hpp - software-pipelined fused step for FP32 and the 16-bit storage
+// forms (included by lbm.hip inside its anonymous namespace).
+//
+// Same step as k_fused (eqs. (HYDRO), (FORCE), (LBEQ)/(LBEQ2) with the
+// velocity shift, the f/g coupling and the counter-term), organised for
+// gfx950's memory system:
+//
+//  * A work-group owns a TX x TY x-y tile and marches up a chunk of z planes.
+//    The own node's stored words of plane k+2 are loaded while plane k is
+//    collided, so every wave keeps one plane of loads in flight during its
+//    arithmetic; the words of k+1 (loaded one plane earlier) give the
+//    moments of k+1 and are kept in registers for its collision.  Three word
+//    sets rotate through the roles (collide, next, in flight) by unrolling the
+//    z loop three times, so no register copies are made.  The one-node ring
+//    around the tile is loaded one plane ahead as well (one ring node per
+//    thread) and only its moments are kept.
+//  * Every load and store uses a wave-uniform 64-bit base (population row
+//    plus plane offset, scalar registers) and a per-thread byte offset within
+//    the plane that is fixed for the whole kernel (nine of them: the node and
+//    its eight x-y neighbours, periodic wrap included), so streaming costs no
+//    vector address arithmetic.
+//  * rho, psi, E and Phi = E - T_lat rho of a plane and its ring sit in one
+//    float4 per node in an LDS ring of four plane slots (one barrier per
+//    plane); the force uses grad Phi = grad E - T_lat grad rho.
+//  * Equilibria are evaluated per pair of opposite directions (shared even
+//    part, odd part of opposite sign).  The 16-bit forms compute in deviation
+//    space: x = pop - pop_ref with pop_ref the rest equilibrium of
+//    (rho_ref, T_ref) (f_ref,l = 3 w_l rho_ref T_lat, g_ref,l = w_l rho_kappa
+//    T_ref for l >= 1), so decoding is a conversion and the equilibria carry
+//    the reference in their node constants.  The rest pair is FP32 and is
+//    updated in remainder form (old value plus what the moving pairs lost,
+//    including the rounding of their 16-bit stores).
+
+namespace pipe {
+
+// Scalars of the pipelined kernel (compute precision FP32).
+struct PParams {
+  int nx, ny, nz, periodic_z;
+  float omega_f, omega_g, tau_nu, G, gravity, inv_cv, gamma, rho_kappa;
+  float T_d, T_u, T_lat;
+  float rho_ref0, T_ref0;   // deviation reference (0 for FP32 storage: absolute values)
+  float Fref, Gref;         // sum over l >= 1 of the reference populations (0 for FP32)
+  int wet_d, wet_u;
+  float psi_wd, psi_wu;
+  int psi_form;
+};
+
+// Stored words: kMove bytes per moving pair; x values are absolute (FP32) or
+// deviations (16-bit forms).
+template <typename C> struct Word;
+template <> struct Word<F32> {
+  using S = float2;
+  static constexpr uint32_t kMove = 8;
+  static constexpr uint32_t kRowOff = 0;   // direction l >= 1 at rows l (in rows of N words)
+  static constexpr bool kDev = false;
+  static __device__ __forceinline__ void dec(S w, float& a, float& b) {
+    a = w.x;
+    b = w.y;
+  }
+};
+template <> struct Word<H16> {
+  using S = uint32_t;
+  static constexpr uint32_t kMove = 4;
+  static constexpr uint32_t kRowOff = 1;   // rows l + 1 (the FP32 rest pair takes rows 0, 1)
+  static constexpr bool kDev = true;
+  static __device__ __forceinline__ void dec(S w, float& a, float& b) {
+    a = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+    b = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  }
+  // encode (a, b); da, db receive the decoded stored values
+  static __device__ __forceinline__ S enc(float a, float b, float& da, float& db) {
+    const _Float16 ha = (_Float16)a, hb = (_Float16)b;
+    da = (float)ha;
+    db = (float)hb;
+    return (uint32_t)__builtin_bit_cast(uint16_t, ha) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+  }
+};
+template <> struct Word<B16> {
+  using S = uint32_t;
+  static constexpr uint32_t kMove = 4;
+  static constexpr uint32_t kRowOff = 1;
+  static constexpr bool kDev = true;
+  static __device__ __forceinline__ void dec(S w, float& a, float& b) {
+    a = __builtin_bit_cast(float, w << 16);
+    b = __builtin_bit_cast(float, w & 0xFFFF0000u);
+  }
+  static __device__ __forceinline__ S enc(float a, float b, float& da, float& db) {
+    const uint32_t ua = bf16_rne(a), ub = bf16_rne(b);
+    da = __builtin_bit_cast(float, ua << 16);
+    db = __builtin_bit_cast(float, ub << 16);
+    return ua | (ub << 16);
+  }
+};
+
+// Index of the x-y offset of direction l among the nine per-thread offsets:
+// 0 node, 1 (+x), 2 (-x), 3 (+y), 4 (-y), 5 (+x+y), 6 (-x-y), 7 (+x-y), 8 (-x+y).
+__host__ __device__ constexpr int xy_slot(int l) {
+  return CX[l] == 0 ? (CY[l] == 0 ? 0 : (CY[l] > 0 ? 3 : 4))
+                    : (CY[l] == 0 ? (CX[l] > 0 ? 1 : 2)
+                                  : (CX[l] > 0 ? (CY[l] > 0 ? 5 : 7) : (CY[l] > 0 ? 8 : 6)));
+}
+
+// Raw buffer access (gfx9 buffer descriptors): the descriptor holds a
+// wave-uniform row start, soffset the wave-uniform plane offset and the
+// VGPR the per-lane byte offset within the plane; no vector address
+// arithmetic.  Rows stay below 4 GiB, so every offset fits in 32 bits and the
+// range check (num_records = 2^32 - 1 bytes) never triggers.  The LLVM
+// buffer intrinsics are declared directly (the clang builtins of this
+// toolchain lower the 64-bit load to a single dword).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ f32x2 buf_ld_v2f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+__device__ uint32_t buf_ld_i32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.i32");
+__device__ void buf_st_v2f32(f32x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f32");
+__device__ void buf_st_i32(uint32_t v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.i32");
+
+using rsrc_t = i32x4;
+__device__ __forceinline__ rsrc_t mkrsrc(const char* row) {
+  const uint64_t p = (uint64_t)row;
+  rsrc_t r;
+  r.x = (int)(uint32_t)p;
+  r.y = (int)((uint32_t)(p >> 32) & 0xFFFFu);   // base bits 47:32, stride 0
+  r.z = -1;                                    // num_records
+  r.w = 0x00020000;                            // gfx9 raw-buffer word 3
+  return r;
+}
+#ifndef LBM_PIPE_STORE_AUX
+#define LBM_PIPE_STORE_AUX 0
+#endif
+template <typename T> struct BufIO;
+template <> struct BufIO<uint32_t> {
+  static __device__ __forceinline__ uint32_t ld(rsrc_t r, uint32_t v, uint32_t s) {
+    return buf_ld_i32(r, (int)v, (int)s, 0);
+  }
+  static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, uint32_t x) {
+    buf_st_i32(x, r, (int)v, (int)s, LBM_PIPE_STORE_AUX);
+  }
+};
+template <> struct BufIO<float2> {
+  static __device__ __forceinline__ float2 ld(rsrc_t r, uint32_t v, uint32_t s) {
+    const f32x2 u = buf_ld_v2f32(r, (int)v, (int)s, 0);
+    return make_float2(u.x, u.y);
+  }
+  static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float2 x) {
+    f32x2 u;
+    u.x = x.x;
+    u.y = x.y;
+    buf_st_v2f32(u, r, (int)v, (int)s, LBM_PIPE_STORE_AUX);
+  }
+};
+// Start of row q (row_bytes apart) of a buffer; the empty asm keeps the
+// compiler from hoisting all 19 row starts into scalar registers for the
+// whole kernel (it recomputes them with two scalar adds instead).
+__device__ __forceinline__ const char* row_start(const char* base, size_t row_bytes, int q) {
+  const char* p = base;
+  asm volatile("" : "+s"(p));
+  return p + (size_t)q * row_bytes;
+}
+
+// The words of one node and one plane: the rest pair and the 18 moving words.
+template <typename C>
+struct NodeWords {
+  float2 w0;
+  typename Word<C>::S w[Q];   // [0] unused
+};
+
+template <typename C, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
+                                                 char* __restrict__ out, PParams P, int ntx,
+                                                 int nty, int kz) {
+  using W = Word<C>;
+  using S = typename W::S;
+  constexpr int NT = TX * TY;
+  constexpr int PW = TX + 2, PN = PW * (TY + 2);
+  constexpr int NS = 4;
+  __shared__ float4 sM[NS][PN];   // (psi, rho, E, Phi) of a plane and its ring
+
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const uint32_t A = (uint32_t)nx * (uint32_t)ny;   // nodes per plane
+  const size_t N = (size_t)A * (size_t)nz;
+  // bytes of one plane of a moving row / of the rest row, and the row starts
+  const size_t plane_m = (size_t)A * W::kMove, plane_0 = (size_t)A * 8u;
+  const size_t row_m = N * W::kMove;
+
+  // XCD-aware tile order (work-groups are dealt round-robin over 8 XCDs)
+  int bid = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int tx = bid % ntx;
+  const int rem = bid / ntx;
+  const int ty = rem % nty;
+  const int zc = rem / nty;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int k0 = zc * kz;
+  const int k1 = min(k0 + kz, nz);
+  const int tw = min(TX, nx - x0), th = min(TY, ny - y0);
+
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = t / TX;
+  const bool active = lx < tw && ly < th;
+  const int i = active ? x0 + lx : x0, j = active ? y0 + ly : y0;
+  const int im = wrap(i - 1, nx), ip = wrap(i + 1, nx), jm = wrap(j - 1, ny), jp = wrap(j + 1, ny);
+  const int own_s = (ly + 1) * PW + (lx + 1);
+
+  // node index within the plane of the node and its x-y neighbours
+  uint32_t xyn[9];
+  xyn[0] = (uint32_t)j * nx + i;
+  xyn[1] = (uint32_t)j * nx + ip;
+  xyn[2] = (uint32_t)j * nx + im;
+  xyn[3] = (uint32_t)jp * nx + i;
+  xyn[4] = (uint32_t)jm * nx + i;
+  xyn[5] = (uint32_t)jp * nx + ip;
+  xyn[6] = (uint32_t)jm * nx + im;
+  xyn[7] = (uint32_t)jm * nx + ip;
+  xyn[8] = (uint32_t)jp * nx + im;
+  uint32_t xyb[9];   // the same in bytes of a moving row
+#pragma unroll
+  for (int q = 0; q < 9; ++q) xyb[q] = xyn[q] * W::kMove;
+
+  // ring node of this thread (one per thread, t < nring)
+  const int nring = 2 * (tw + 2) + 2 * th;
+  const bool ringt = t < nring;
+  int rx = 0, ry = 0;
+  if (ringt) {
+    if (t < tw + 2) {
+      rx = t - 1;
+      ry = -1;
+    } else if (t < 2 * (tw + 2)) {
+      rx = t - (tw + 2) - 1;
+      ry = th;
+    } else {
+      const int q = t - 2 * (tw + 2);
+      rx = q < th ? -1 : tw;
+      ry = q < th ? q : q - th;
+    }
+  }
+  const uint32_t ring_n = (uint32_t)wrap(y0 + ry, ny) * nx + (uint32_t)wrap(x0 + rx, nx);
+  const int ring_s = (ry + 1) * PW + (rx + 1);
+
+  const bool walls = !P.periodic_z;
+  auto phys = [&](int kp) { return kp < 0 ? kp + nz : (kp >= nz ? kp - nz : kp); };
+  auto slot = [&](int kp) { return (kp - k0 + NS) % NS; };
+  auto exists = [&](int kp) { return walls ? (kp >= 0 && kp < nz) : true; };
+
+  // load the words of node offsets (vm: moving rows, v0: rest row) of
+  // physical plane kp.  Every lane of the wave loads (lanes without a node of
+  // their own read a valid node of the tile), so there is no divergence.
+  auto load = [&](int kp, uint32_t vm, uint32_t v0, NodeWords<C>& nw) {
+    nw.w0 = BufIO<float2>::ld(mkrsrc(row_start(in, row_m, 0)), v0, (uint32_t)kp * (uint32_t)plane_0);
+#pragma unroll
+    for (int l = 1; l < Q; ++l)
+      nw.w[l] = BufIO<S>::ld(mkrsrc(row_start(in, row_m, l + (int)W::kRowOff)), vm,
+                             (uint32_t)kp * (uint32_t)plane_m);
+  };
+  // the ring loads are issued by the waves that hold ring threads only
+  const bool ring_wave = __builtin_amdgcn_readfirstlane(t) < nring;
+  auto load_all = [&](int kp, NodeWords<C>& nw, NodeWords<C>& nr) {
+    load(kp, xyb[0], xyn[0] * 8u, nw);
+    if (ring_wave) load(kp, ring_n * W::kMove, ring_n * 8u, nr);
+  };
+  // moments (rho, E) of a node's words, in a fixed order
+  auto node_moments = [&](const NodeWords<C>& nw, float& rho, float& E) {
+    float sf = 0.f, sg = 0.f;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      float a, b;
+      W::dec(nw.w[l], a, b);
+      sf += a;
+      sg += b;
+    }
+    rho = nw.w0.x + (P.Fref + sf);
+    E = nw.w0.y + (P.Gref + sg);
+  };
+  auto put = [&](int s, int q, float rho, float E) {
+    sM[s][q] = make_float4(psi_of<float>(rho, P.psi_form), rho, E, E - P.T_lat * rho);
+  };
+  // moments of a plane's own and ring nodes into its slot
+  auto fill = [&](int s, const NodeWords<C>& own, const NodeWords<C>& ring) {
+    if (active) {
+      float rho, E;
+      node_moments(own, rho, E);
+      put(s, own_s, rho, E);
+    }
+    if (ringt) {
+      float rho, E;
+      node_moments(ring, rho, E);
+      put(s, ring_s, rho, E);
+    }
+  };
+  // wall ghost slot: psi mirrored (or of the prescribed wall density), rho,
+  // E and Phi extrapolated linearly through the wall
+  auto ghost = [&](int sg, int sw, int si, int wet, float psi_w) {
+    for (int q = t; q < PN; q += NT) {
+      const float4 a = sM[sw][q], b = sM[si][q];
+      sM[sg][q] = make_float4(wet ? psi_w : a.x, 2.f * a.y - b.y, 2.f * a.z - b.z,
+                              2.f * a.w - b.w);
+    }
+  };
+
+  // collision of the own node of plane k (words nw) and push streaming
+  auto collide = [&](int k, const NodeWords<C>& nw) {
+    const int sm = slot(k - 1), s0 = slot(k), sp = slot(k + 1);
+    float xf[Q], xg[Q];
+#pragma unroll
+    for (int l = 1; l < Q; ++l) W::dec(nw.w[l], xf[l], xg[l]);
+    const float4 me = sM[s0][own_s];
+    const float psi = me.x, rho = me.y, E = me.z;
+    // W-stencil gradients of psi, E and Phi, accumulated over pairs of
+    // opposite neighbours (the same sums as grad_w, in pair order)
+    float gpx = 0.f, gpy = 0.f, gpz = 0.f, gEx = 0.f, gEy = 0.f, gEz = 0.f;
+    float gFx = 0.f, gFy = 0.f, gFz = 0.f;
+#pragma unroll
+    for (int l = 1; l < Q; l += 2) {
+      const int lb = l + 1;
+      const int sa = CZ[l] < 0 ? sm : (CZ[l] > 0 ? sp : s0);
+      const int sb = CZ[lb] < 0 ? sm : (CZ[lb] > 0 ? sp : s0);
+      const float4 a = sM[sa][own_s + CY[l] * PW + CX[l]];
+      const float4 b = sM[sb][own_s + CY[lb] * PW + CX[lb]];
+      const float wq = l < 7 ? (1.f / 6.f) : (1.f / 12.f);
+      const float dp = wq * (a.x - b.x), dE = wq * (a.z - b.z), dF = wq * (a.w - b.w);
+      if (CX[l]) { gpx += CX[l] * dp; gEx += CX[l] * dE; gFx += CX[l] * dF; }
+      if (CY[l]) { gpy += CY[l] * dp; gEy += CY[l] * dE; gFy += CY[l] * dF; }
+      if (CZ[l]) { gpz += CZ[l] * dp; gEz += CZ[l] * dE; gFz += CZ[l] * dF; }
+    }
+    float jx, jy, jz;
+    momentum<float>(xf, jx, jy, jz);
+    const float gp = -P.G * psi;
+    const float Fx = gp * gpx - gFx;
+    const float Fy = gp * gpy - gFy;
+    const float Fz = gp * gpz - gFz - P.gravity * rho;
+    const float ir = 1.f / rho;
+    const float ux = (jx + P.tau_nu * Fx) * ir, uy = (jy + P.tau_nu * Fy) * ir,
+                uz = (jz + P.tau_nu * Fz) * ir;
+    const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
+    const float T = E * ir;
+    const float Ssrc = (vx * gEx + vy * gEy + vz * gEz) * P.inv_cv;
+    const float gE = P.gamma * E;
+    // node constants of the equilibria (deviation references folded in)
+    const float Af = 3.f * P.T_lat * (rho - P.rho_ref0) - 1.5f * rho * (ux * ux + uy * uy + uz * uz);
+    const float Ag = P.rho_kappa * (T - P.T_ref0) - 1.5f * gE * (vx * vx + vy * vy + vz * vz);
+
+    float rf = 0.f, rg = 0.f;
+    // plane offsets of k - 1, k, k + 1 (wrapped when z is periodic) and the
+    // wall planes (uniform over the work-group)
+    const uint32_t so_m = (uint32_t)phys(k - 1) * (uint32_t)plane_m;
+    const uint32_t so_0 = (uint32_t)k * (uint32_t)plane_m;
+    const uint32_t so_p = (uint32_t)phys(k + 1) * (uint32_t)plane_m;
+    const bool wall_d = walls && k == 0, wall_u = walls && k == nz - 1;
+    // store pair (a, b) as direction q of node slot xs at plane offset so
+    auto store = [&](int q, uint32_t so, int xs, float a, float b) {
+      const rsrc_t r = mkrsrc(row_start(out, row_m, q + (int)W::kRowOff));
+      if constexpr (W::kDev) {
+        float da, db;
+        const S wv = W::enc(a, b, da, db);
+        rf += a - da;
+        rg += b - db;
+        BufIO<S>::st(r, xyb[xs], so, wv);
+      } else {
+        BufIO<S>::st(r, xyb[xs], so, make_float2(a, b));
+      }
+    };
+#pragma unroll
+    for (int l = 1; l < Q; l += 2) {
+      const int lb = l + 1;   // opposite of l in this velocity order
+      const float w = wlat<float>(l);
+      const float cu = float(CX[l]) * ux + float(CY[l]) * uy + float(CZ[l]) * uz;
+      const float cv = float(CX[l]) * vx + float(CY[l]) * vy + float(CZ[l]) * vz;
+      const float wr = w * rho, we = w * gE;
+      const float fs = fmaf(4.5f * wr * cu, cu, w * Af), fa = 3.f * wr * cu;
+      const float gs = fmaf(4.5f * we * cv, cv, w * Ag), ga = 3.f * we * cv;
+      const float wS = w * Ssrc;
+      const float dfa = P.omega_f * (xf[l] - (fs + fa));
+      const float dfb = P.omega_f * (xf[lb] - (fs - fa));
+      const float dga = fmaf(P.omega_g, xg[l] - (gs + ga), -wS);
+      const float dgb = fmaf(P.omega_g, xg[lb] - (gs - ga), -wS);
+      const float fna = xf[l] - dfa, fnb = xf[lb] - dfb;
+      const float gna = xg[l] - dga, gnb = xg[lb] - dgb;
+      // what the pairs give up (the 16-bit stores add their rounding)
+      rf += dfa + dfb;
+      rg += dga + dgb;
+      // push: direction l from node x goes to x + c_l; at a wall it comes
+      // back to x in the opposite direction (anti-bounce-back for g about
+      // w_l rho_kappa T_wall)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int d = h ? lb : l;
+        const float fn = h ? fnb : fna, gn = h ? gnb : gna;
+        if (CZ[d] == 0) {
+          store(d, so_0, xy_slot(d), fn, gn);
+        } else if (CZ[d] > 0) {
+          if (wall_u)
+            store(OPP[d], so_0, 0, fn, -gn + 2.f * w * P.rho_kappa * (P.T_u - P.T_ref0));
+          else
+            store(d, so_p, xy_slot(d), fn, gn);
+        } else {
+          if (wall_d)
+            store(OPP[d], so_0, 0, fn, -gn + 2.f * w * P.rho_kappa * (P.T_d - P.T_ref0));
+          else
+            store(d, so_m, xy_slot(d), fn, gn);
+        }
+      }
+    }
+    // rest pair, remainder form: mass kept, energy + S
+    BufIO<float2>::st(mkrsrc(row_start(out, row_m, 0)), xyn[0] * 8u, (uint32_t)k * (uint32_t)plane_0,
+                      make_float2(nw.w0.x + rf, nw.w0.y + (Ssrc + rg)));
+  };
+
+  NodeWords<C> WA, WB, WC, RR;
+  // prologue: moments of plane k0 - 1 and k0, words of k0 kept, k0 + 1 in flight
+  {
+    NodeWords<C> tmp;
+    const int km = k0 - 1;
+    if (exists(km)) {
+      load_all(phys(km), tmp, RR);
+      fill(slot(km), tmp, RR);
+    }
+    load_all(k0, WA, RR);
+    fill(slot(k0), WA, RR);
+    const int kn = k0 + 1;
+    if (exists(kn)) load_all(phys(kn), WB, RR);
+  }
+
+  // one plane: prefetch k+2, moments of k+1, barrier, collide k
+  auto iter = [&](int k, NodeWords<C>& Wc, NodeWords<C>& Wn, NodeWords<C>& Wp) {
+    const int kn = k + 1, kp = k + 2;
+    const bool pre = kp <= k1 && exists(kp);
+    if (exists(kn)) fill(slot(kn), Wn, RR);
+    if (pre) load_all(phys(kp), Wp, RR);
+    __syncthreads();
+    if (walls && (k == 0 || kn == nz)) {
+      if (k == 0) ghost(slot(-1), slot(0), slot(1), P.wet_d, P.psi_wd);
+      if (kn == nz) ghost(slot(kn), slot(k), slot(k - 1), P.wet_u, P.psi_wu);
+      __syncthreads();
+    }
+    if (active) collide(k, Wc);
+  };
+
+  for (int k = k0; k < k1; k += 3) {
+    iter(k, WA, WB, WC);
+    if (k + 1 < k1) iter(k + 1, WB, WC, WA);
+    if (k + 2 < k1) iter(k + 2, WC, WA, WB);
+  }
+}
+
+}  // namespace pipe

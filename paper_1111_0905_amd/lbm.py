@@ -15,7 +15,7 @@ from dataclasses import dataclass, fields
 import numpy as np
 
 LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_BF16DEV = 0, 1, 2, 3
-LBM_KERNEL_FUSED, LBM_KERNEL_REFERENCE, LBM_KERNEL_FUSED_RELOAD = 0, 1, 2
+LBM_KERNEL_FUSED, LBM_KERNEL_REFERENCE, LBM_KERNEL_FUSED_RELOAD, LBM_KERNEL_PIPELINED = 0, 1, 2, 3
 STORAGE = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16dev": LBM_FP16DEV, "bf16dev": LBM_BF16DEV}
 LBM_Q_RHO, LBM_Q_T, LBM_Q_VZ, LBM_Q_HEATFLUX = 0, 1, 2, 3
 
