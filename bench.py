@@ -10,9 +10,12 @@ populations resident in HBM.
 
 Prints one JSON line: MLUPS, ms per step, the roofline of the step kernel
 (algorithmic bytes = one read and one write of each node's stored
-populations: 2 x 152 B in FP32, 2 x 80 B in the 16-bit forms),
-the FP16/BF16-deviation storage forms beside it, and the FP64 CPU oracle
-timed on a bounded sample on the host.
+populations: 2 x 152 B in FP32, 2 x 80 B in the 16-bit forms) against the
+8 TB/s of the data sheet and against two references timed in the same
+process with the library's plain streaming kernels (a 16-byte-per-lane copy
+of 8 GiB each way, and the step's 19-row read/write pattern without its
+arithmetic), the FP16/BF16-deviation storage forms beside it, and the FP64
+CPU oracle timed on a bounded sample on the host.
 """
 import argparse
 import json
@@ -98,7 +101,7 @@ def source_hash():
 def measured_traffic(storage, n):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on this very kernel source and workload (else None)."""
-    path = os.path.join(ROOT, "profiles", f"k_fused_{storage}_{n}cubed_counters.json")
+    path = os.path.join(ROOT, "profiles", f"step_{storage}_{n}cubed_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -106,6 +109,44 @@ def measured_traffic(storage, n):
     if d.get("source_sha256") != source_hash():
         return None
     return d["traffic_bytes_per_launch"]
+
+
+def bandwidth_references(lbm, gib=8, reps=5):
+    """HBM references timed in this process with the library's plain
+    streaming kernels: the 16-byte-per-lane copy of `gib` GiB each way (plain
+    and non-temporal; the faster counts) and the step's row pattern without
+    arithmetic (19 rows read and written per thread, 400 MiB each, 7.4 GiB
+    each way).  GB/s of reads plus writes."""
+    import torch
+    nbytes = gib << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    copy = {}
+    for nt in (False, True):
+        ms = timed(lambda: lbm.lbm_stream_copy(a, b, nbytes, nt))
+        copy["nontemporal" if nt else "plain"] = 2 * nbytes / ms / 1e6
+    row = 400 << 20
+    ms = timed(lambda: lbm.lbm_stream_rows(a, b, 19, row, row))
+    rows19 = 2 * 19 * row / ms / 1e6
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_gbs": max(copy.values()), "copy_plain_gbs": copy["plain"],
+            "copy_nontemporal_gbs": copy["nontemporal"], "rows19_gbs": rows19}
 
 
 def cpu_baseline(seconds=15.0, n=64, max_steps=None):
@@ -145,9 +186,11 @@ def main():
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--no-16bit", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-references", action="store_true",
+                    help="skip the copy and row-pattern bandwidth references")
     ap.add_argument("--sweep", action="store_true", help="time kernel/tile variants")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a plain 2 GiB device copy (calibrates HBM byte counters)")
+                    help="only run the library's plain 2 GiB copy (calibrates HBM byte counters)")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 CPU oracle at 32^3, 64^3 (100 steps) and 128^3 "
                          "(20 steps), one JSON line each")
@@ -159,18 +202,22 @@ def main():
         return
 
     if args.copy_probe:
+        # the library's plain 16-byte copy of 2 GiB (calibrates the HBM byte
+        # counters: FETCH_SIZE and WRITE_SIZE of a copy of known size)
         import torch
+        from paper_1111_0905_amd import lbm
+        lbm.load_library()
         nbytes = 2 << 30
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            lbm.lbm_stream_copy(src, dst, nbytes)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         reps = 10
         for _ in range(reps):
-            dst.copy_(src)
+            lbm.lbm_stream_copy(src, dst, nbytes)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
@@ -194,8 +241,8 @@ def main():
     rho0 = lbm.lbm_seeded_density(n, n, n, 1234, rho_mean, 0.01).reshape(-1)
 
     if args.sweep:
-        combos = [(0, 32, 16), (0, 64, 8), (0, 64, 4), (0, 64, 2), (0, 32, 8), (2, 64, 16),
-                  (2, 64, 8), (2, 64, 4), (2, 32, 16)]
+        combos = [(3, 128, 4), (3, 64, 8), (3, 32, 16), (3, 32, 8), (0, 32, 16), (0, 64, 8),
+                  (2, 64, 16), (2, 64, 8)]
         for kernel, tx, ty in combos:
             for zc in (0,):
                 r, _ = run_storage(lbm, n, args.storage, args.steps, args.warmup, rho0,
@@ -215,7 +262,16 @@ def main():
             extra[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                          "achieved_gbs": round(r["achieved_gbs"], 1),
                          "frac_of_peak": round(r["achieved_gbs"] / PEAK_HBM_GBS, 4),
+                         # on 2 x 76 B per node (all 38 populations in 16 bits)
+                         "frac_of_peak_152B": round(152 * n ** 3 / (r["ms_per_step"] * 1e-3) / 1e9
+                                                    / PEAK_HBM_GBS, 4),
                          "speedup_vs_fp32": round(r["mlups"] / main_res["mlups"], 3)}
+    refs = None if args.no_references else bandwidth_references(lbm)
+    if refs:
+        print(f"bench: copy {refs['copy_gbs']:.0f} GB/s, 19-row pattern {refs['rows19_gbs']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        for st, r in extra.items():
+            r["frac_of_copy"] = round(r["achieved_gbs"] / refs["copy_gbs"], 4)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     out = {
@@ -237,7 +293,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(main_res["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_res["achieved_gbs"] / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(args.storage, n)},
+                     "traffic": measured_traffic(args.storage, n),
+                     "copy_gbs": round(refs["copy_gbs"], 1) if refs else None,
+                     "frac_of_copy": round(main_res["achieved_gbs"] / refs["copy_gbs"], 4) if refs else None,
+                     "rows19_gbs": round(refs["rows19_gbs"], 1) if refs else None,
+                     "frac_of_rows19": round(main_res["achieved_gbs"] / refs["rows19_gbs"], 4) if refs else None},
+        "bandwidth_references": refs,
         "storage_forms": extra,
         "cpu_baseline": cpu,
     }

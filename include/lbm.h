@@ -312,6 +312,29 @@ int lbm_adjoint_init_rho(lbm_handle* h, const double* adj0, const double* T0, do
 /* Release the handle (the workspace stays the caller's). */
 void lbm_destroy(lbm_handle* h);
 
+/*
+ * Bandwidth references for the roofline of the step (not part of the
+ * method): plain streaming kernels that show what HBM delivers on this
+ * device, timed beside the step by the caller.
+ *
+ * lbm_stream_copy: dst[0, bytes) = src[0, bytes), one 16-byte vector per
+ *   thread; nontemporal != 0 marks the loads and stores non-temporal.
+ *   src, dst: device, 16-byte aligned, not overlapping; bytes a positive
+ *   multiple of 16.  Asynchronous on stream.
+ * lbm_stream_rows: the step's streaming pattern without its arithmetic:
+ *   every thread reads 8 bytes at the same offset of each of `rows` rows
+ *   (row_stride bytes apart) and writes them to the same places of dst,
+ *   all loads before the stores (the step reads 19 population rows and
+ *   writes 19).  rows: 1, 2, 4 or 19; row_bytes: bytes moved per row
+ *   (multiple of 8); row_stride >= row_bytes (multiple of 8); src, dst:
+ *   device, 8-byte aligned, rows * row_stride bytes each, not overlapping.
+ *   Asynchronous on stream.
+ * Both return LBM_EINVAL for arguments outside these ranges.
+ */
+int lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t nontemporal, void* stream);
+int lbm_stream_rows(const void* src, void* dst, int32_t rows, size_t row_stride, size_t row_bytes,
+                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

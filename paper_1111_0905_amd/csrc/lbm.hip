@@ -480,6 +480,10 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
 
 #include "pipe.hpp"
 
+// ---------------------------------------------------------------- bandwidth references
+
+#include "probe.hpp"
+
 // ---------------------------------------------------------------- diagnostics
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -1894,6 +1898,49 @@ int lbm_adjoint_qbot(lbm_handle* h, const double* state, double weight, double* 
 int lbm_adjoint_init_rho(lbm_handle* h, const double* adj0, const double* T0, double* dJ_drho0) {
   if (!h || !adj0 || !dJ_drho0) return fail(LBM_EINVAL, "NULL argument");
   return do_adjoint_init<double>(h, adj0, T0, dJ_drho0);
+}
+
+int lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t nontemporal, void* stream) {
+  if (!src || !dst) return fail(LBM_EINVAL, "NULL argument");
+  if (bytes == 0 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+    return fail(LBM_EINVAL, "bytes must be a positive multiple of 16 and both pointers 16-byte aligned");
+  const size_t n = bytes / 16;
+  const size_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffffULL) return fail(LBM_EINVAL, "copy too large");
+  if (nontemporal)
+    hipLaunchKernelGGL(k_copy16<true>, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                       (const float4*)src, (float4*)dst, n);
+  else
+    hipLaunchKernelGGL(k_copy16<false>, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                       (const float4*)src, (float4*)dst, n);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_stream_rows(const void* src, void* dst, int32_t rows, size_t row_stride, size_t row_bytes,
+                    void* stream) {
+  if (!src || !dst) return fail(LBM_EINVAL, "NULL argument");
+  if (rows != 1 && rows != 2 && rows != 4 && rows != 19)
+    return fail(LBM_EINVAL, "rows must be 1, 2, 4 or 19");
+  if (row_bytes == 0 || row_bytes % 8 || row_stride % 8 || row_stride < row_bytes ||
+      ((uintptr_t)src | (uintptr_t)dst) % 8)
+    return fail(LBM_EINVAL, "row_bytes > 0, row_bytes and row_stride multiples of 8, row_stride >= "
+                            "row_bytes, pointers 8-byte aligned");
+  const size_t n = row_bytes / 8;
+  const size_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffffULL) return fail(LBM_EINVAL, "rows too long");
+  auto go = [&](auto R) {
+    hipLaunchKernelGGL((k_rows<decltype(R)::value>), dim3((unsigned)grid), dim3(256), 0,
+                       (hipStream_t)stream, (const char*)src, (char*)dst, row_stride, n);
+  };
+  switch (rows) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: go(std::integral_constant<int, 19>{}); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
 }
 
 void lbm_destroy(lbm_handle* h) { delete h; }

@@ -115,6 +115,10 @@ def load_library(path: str = _LIB_PATH):
         "lbm_structure_functions": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, D],
                                     ctypes.c_int),
+        "lbm_stream_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                             ctypes.c_void_p], ctypes.c_int),
+        "lbm_stream_rows": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t,
+                             ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
         "lbm_histogram": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                            ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                            ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
@@ -301,6 +305,36 @@ def lbm_adjoint_init_rho(h: _Handle, adj0, T0=None, out=None):
     _check(load_library().lbm_adjoint_init_rho(h.h, _dev_ptr(adj0, torch.float64, 38 * h.p.n),
                                                T0p, _dev_ptr(out, torch.float64, h.p.n)))
     return out
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _raw_ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous cuda tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def lbm_stream_copy(src, dst, nbytes: int, nontemporal: bool = False, stream=None):
+    """Plain device copy of nbytes (bandwidth reference; asynchronous)."""
+    if src.numel() * src.element_size() < nbytes or dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("buffers smaller than nbytes")
+    _check(load_library().lbm_stream_copy(_raw_ptr(src), _raw_ptr(dst), int(nbytes),
+                                          1 if nontemporal else 0, _stream_ptr(stream)))
+
+
+def lbm_stream_rows(src, dst, rows: int, row_stride: int, row_bytes: int, stream=None):
+    """The step's row-streaming pattern without arithmetic (bandwidth
+    reference; asynchronous)."""
+    need = rows * row_stride
+    if src.numel() * src.element_size() < need or dst.numel() * dst.element_size() < need:
+        raise ValueError("buffers smaller than rows * row_stride")
+    _check(load_library().lbm_stream_rows(_raw_ptr(src), _raw_ptr(dst), int(rows), int(row_stride),
+                                          int(row_bytes), _stream_ptr(stream)))
 
 
 def lbm_destroy(h: _Handle):

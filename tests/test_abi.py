@@ -89,3 +89,28 @@ def test_null_arguments_of_diagnostics(lib):
     assert lib.lbm_histogram(None, 0, 1, 0, 0.0, 1.0, 1, -1, 0.0, 1.0, 1, None, None, None) == -1
     assert lib.lbm_seeded_density(4, 4, 4, 1, 1.0, 0.1, None, None) == -1
     assert lib.lbm_structure_work_bytes(None, 0, 1, 1) == 0
+
+
+def test_pipelined_kernel_validation(lib):
+    from paper_1111_0905_amd import lbm
+    ok = lbm.Params(64, 32, 16, storage=lbm.LBM_FP16DEV, kernel=lbm.LBM_KERNEL_PIPELINED,
+                    tile_x=128, tile_y=4)
+    assert lbm.lbm_workspace_bytes(ok) > 0
+    for bad in [dict(storage=lbm.LBM_FP64), dict(tile_x=64, tile_y=16), dict(tile_x=32, tile_y=32)]:
+        kw = dict(storage=lbm.LBM_FP32, kernel=lbm.LBM_KERNEL_PIPELINED)
+        kw.update(bad)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_workspace_bytes(lbm.Params(64, 32, 16, **kw))
+
+
+def test_stream_references_reject_bad_arguments(lib):
+    """Argument checks of the bandwidth references happen before any launch."""
+    fake = ctypes.c_void_p(4096)
+    assert lib.lbm_stream_copy(None, fake, 16, 0, None) == -1
+    assert lib.lbm_stream_copy(fake, fake, 0, 0, None) == -1
+    assert lib.lbm_stream_copy(fake, fake, 24, 0, None) == -1           # not a multiple of 16
+    assert lib.lbm_stream_copy(ctypes.c_void_p(4104), fake, 32, 0, None) == -1   # misaligned
+    assert lib.lbm_stream_rows(fake, fake, 3, 64, 64, None) == -1       # unsupported row count
+    assert lib.lbm_stream_rows(fake, fake, 19, 32, 64, None) == -1      # stride < row bytes
+    assert lib.lbm_stream_rows(fake, fake, 19, 64, 12, None) == -1      # not a multiple of 8
+    assert b"rows" in lib.lbm_last_error() or b"row" in lib.lbm_last_error()
