@@ -221,6 +221,25 @@ int lbm_moments(lbm_handle* h, double* totals, double* fields);
  */
 int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, double* T_z);
 
+/*
+ * Plane profile of the pressure work, the right-hand side of the layer heat
+ * balance eq. (heat2) and the integrand of the constraint eq. (flux),
+ * Nu(z) - Nu(0) = -integral_0^z <P d_j u_j>:
+ *   pw_z[k] = horizontal mean over plane k of P d_j v_j,
+ * with P = rho T + (G/2) psi(rho)^2 the bulk equation of state (text after
+ * eq. (ns); psi of the handle's psi_form), v = (j + F/2)/rho the physical
+ * velocity and d_j v_j its divergence on the W stencil of eq. (FORCE)
+ * (central differences; at the no-slip walls the ghost planes hold the
+ * negative mirror image of v, periodic otherwise), all in FP64 from the
+ * moment fields of lbm_moments.
+ *   work: device, >= 5 * nx * ny * nz doubles, caller-owned; receives the
+ *     moment fields (rho, v_x, v_y, v_z, T) as lbm_moments writes them.
+ *   pw_z: host, nz doubles.
+ * Synchronises the stream.  LBM_EWORKSPACE if work is too small;
+ * LBM_ENUMERIC as lbm_moments.
+ */
+int lbm_pressure_work(lbm_handle* h, double* work, size_t work_bytes, double* pw_z);
+
 /* node quantities for lbm_histogram */
 enum {
   LBM_Q_RHO = 0,       /* density */

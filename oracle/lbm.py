@@ -399,6 +399,36 @@ def totals(p: Params, f, g) -> torch.Tensor:
     return torch.stack([m["rho"].sum(), P[0], P[1], P[2], m["E"].sum(), rU.sum()])
 
 
+def bulk_pressure(p: Params, rho, T):
+    """Equation of state (text after eq. (ns)): P = P0 + P_NI with P0 = rho T
+    and P_NI = (G/2) psi^2, i.e. (G/2) exp(-2/rho) for the paper's psi (its
+    G exp(-2/rho) with the factor 1/2 of the W-normalised force)."""
+    psi = pseudopotential(rho, p.psi_form)
+    return rho * T + 0.5 * p.G * psi * psi
+
+
+def divergence(p: Params, v: torch.Tensor) -> torch.Tensor:
+    """sum_l W_l c_l . v(x + c_l): the W-stencil divergence (central, like
+    the gradients).  At the no-slip walls the ghost planes hold the negative
+    mirror image of every velocity component (v = 0 on the half-way wall)."""
+    vp = _pad_z(v, walls=not p.periodic_z, odd=True)
+    s = torch.zeros(tuple(v.shape[1:]), dtype=v.dtype)
+    for l in range(1, Q19):
+        cv = sum(C_INT[l][a] * _at(vp[a], C_INT[l]) for a in range(3) if C_INT[l][a])
+        s = s + W_FOR[l] * cv
+    return s
+
+
+def pressure_work(p: Params, f, g):
+    """Horizontal average of P d_j u_j at each k: the source of the layer
+    heat balance eq. (heat2) and the integrand of the constraint eq. (flux),
+    Nu(z) - Nu(0) = -integral_0^z <P d_j u_j>.  u is the physical velocity
+    v = (j + F/2)/rho, P the bulk equation of state."""
+    m = macroscopic(p, f, g)
+    P = bulk_pressure(p, m["rho"], m["T"])
+    return (P * divergence(p, m["v"])).mean(dim=(1, 2))
+
+
 def plane_profiles(p: Params, f, g):
     """Horizontal averages at each k: T-bar(k) and <rho U v_z>(k)."""
     m = macroscopic(p, f, g)

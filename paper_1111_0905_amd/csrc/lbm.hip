@@ -785,6 +785,50 @@ __global__ __launch_bounds__(256) void k_plane(const typename C::S* __restrict__
   }
 }
 
+// <P d_j v_j>(k) from the moment fields (rho, vx, vy, vz, T): P = rho T +
+// (G/2) psi^2 (the bulk equation of state), the divergence of the physical
+// velocity on the W stencil with the ghost planes of the walls holding the
+// negative mirror image (v = 0 on the half-way wall), periodic otherwise.
+// One block per plane, FP64, fixed summation order.
+__global__ __launch_bounds__(256) void k_pwork(const double* __restrict__ fl, int nx, int ny,
+                                               int nz, int periodic, double G, int psi_form,
+                                               double* __restrict__ prof) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  const size_t N = (size_t)nx * ny * nz;
+  const int plane = nx * ny;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < plane; q += blockDim.x) {
+    const int i = q % nx, j = q / nx;
+    const size_t n = ((size_t)k * ny + j) * nx + i;
+    const double rho = fl[n], T = fl[4 * N + n];
+    const double psi = psi_form ? 1.0 - exp(-rho) : exp(-1.0 / rho);
+    const double Pn = rho * T + 0.5 * G * psi * psi;
+    double div = 0.0;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      const int ii = wrap(i + CX[l], nx), jj = wrap(j + CY[l], ny);
+      int kk = k + CZ[l];
+      double sgn = 1.0;
+      if (kk < 0 || kk >= nz) {
+        if (periodic) {
+          kk = kk < 0 ? kk + nz : kk - nz;
+        } else {
+          kk = kk < 0 ? 0 : nz - 1;
+          sgn = -1.0;
+        }
+      }
+      const size_t m = ((size_t)kk * ny + jj) * nx + ii;
+      const double cv = (double)CX[l] * fl[N + m] + (double)CY[l] * fl[2 * N + m] +
+                        (double)CZ[l] * fl[3 * N + m];
+      div += (l < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * sgn * cv;
+    }
+    acc += Pn * div;
+  }
+  const double sum = block_sum(acc, sh);
+  if (threadIdx.x == 0) prof[k] = sum / plane;
+}
+
 // Nusselt numbers from the plane profiles; out = [nu_bot, nu_top, nu_z[nz], T_z[nz]].
 __global__ void k_finish_nusselt(const double* __restrict__ prof, int nz, double T_d, double T_u,
                                  double kappa, double* __restrict__ out) {
@@ -1664,6 +1708,20 @@ template <typename C> struct SfFn {
     return do_structure<C>(h, k0, k1, q, rmax, w, o);
   }
 };
+template <typename C> struct PworkFn {
+  static int run(lbm_handle* h, double* work, double* out) {
+    double tot[6];
+    int rc = do_moments<C>(h, tot, work);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_pwork, dim3(h->p.nz), dim3(256), 0, h->stream, work, h->p.nx, h->p.ny,
+                       h->p.nz, h->p.periodic_z ? 1 : 0, h->p.G, h->p.psi_form, h->prof);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, h->prof, sizeof(double) * (size_t)h->p.nz, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+  }
+};
 template <typename C> struct NuFn {
   static int run(lbm_handle* h, double* a, double* b, double* c, double* d) {
     return do_nusselt<C>(h, a, b, c, d);
@@ -1821,6 +1879,13 @@ int lbm_nusselt(lbm_handle* h, double* nu_bot, double* nu_top, double* nu_z, dou
   if (h->p.periodic_z) return fail(LBM_EINVAL, "Nusselt numbers need walls");
   if (!(h->p.T_d != h->p.T_u)) return fail(LBM_EINVAL, "Nusselt numbers need T_d != T_u");
   return dispatch<NuFn>(h->p.storage, h, nu_bot, nu_top, nu_z, T_z);
+}
+
+int lbm_pressure_work(lbm_handle* h, double* work, size_t work_bytes, double* pw_z) {
+  if (!h || !work || !pw_z) return fail(LBM_EINVAL, "NULL argument");
+  if (work_bytes < 5 * h->L.N * sizeof(double))
+    return fail(LBM_EWORKSPACE, "work buffer smaller than 5 * nx * ny * nz doubles");
+  return dispatch<PworkFn>(h->p.storage, h, work, pw_z);
 }
 
 int lbm_histogram(lbm_handle* h, int32_t k0, int32_t k1, int32_t qx, double x_lo, double x_hi,

@@ -115,6 +115,7 @@ def load_library(path: str = _LIB_PATH):
         "lbm_structure_functions": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, D],
                                     ctypes.c_int),
+        "lbm_pressure_work": ([H, ctypes.c_void_p, ctypes.c_size_t, D], ctypes.c_int),
         "lbm_stream_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
                              ctypes.c_void_p], ctypes.c_int),
         "lbm_stream_rows": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t,
@@ -307,6 +308,16 @@ def lbm_adjoint_init_rho(h: _Handle, adj0, T0=None, out=None):
     return out
 
 
+def lbm_pressure_work(h: _Handle) -> np.ndarray:
+    """<P d_j v_j>(k), nz doubles (eq. (heat2), eq. (flux))."""
+    import torch
+    work = torch.empty(5 * h.p.n, dtype=torch.float64, device=h.workspace.device)
+    out = (ctypes.c_double * h.p.nz)()
+    _check(load_library().lbm_pressure_work(h.h, ctypes.c_void_p(work.data_ptr()),
+                                            5 * h.p.n * 8, out))
+    return np.array(out[:])
+
+
 def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -376,6 +387,9 @@ class Lattice:
 
     def nusselt(self):
         return lbm_nusselt(self.h)
+
+    def pressure_work(self):
+        return lbm_pressure_work(self.h)
 
     def histogram(self, k0, k1, qx, x_range, nx_bins, qy=-1, y_range=(0.0, 1.0), ny_bins=1):
         return lbm_histogram(self.h, k0, k1, qx, x_range, nx_bins, qy, y_range, ny_bins)
