@@ -192,8 +192,27 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes,
 int lbm_seeded_density(int32_t nx, int32_t ny, int32_t nz, uint64_t seed, double rho_mean,
                        double noise_amp, double* rho0, void* stream);
 
-/* Advance n >= 0 time steps (asynchronous on the handle's stream). */
+/*
+ * Advance n >= 0 time steps of eqs. (LBEQ)/(LBEQ2): per step one collision
+ * (BGK with the velocity-shifted f equilibrium, the pseudopotential force
+ * of eq. (FORCE) with the thermal and gravity forces, the g equilibrium with
+ * the counter-term) and one streaming with the walls, on the handle's
+ * stream (asynchronous unless the numeric guard below is on).
+ */
 int lbm_step(lbm_handle* h, int64_t n);
+
+/*
+ * Numeric guard of lbm_step (failure detection; the paper has none).  With
+ * every > 0, after each step whose count since lbm_init / lbm_set_state is a
+ * multiple of `every`, lbm_step reads the state once more (FP64 sums of the
+ * stored populations per node), synchronises the stream and returns
+ * LBM_ENUMERIC (message: the step and what failed) if a node's populations
+ * sum to a non-finite value or to rho <= 0, or if the stored mass differs
+ * from its value at the first check (after lbm_set_check or lbm_set_state)
+ * by more than mass_tol relative.  every = 0 turns the guard off (default).
+ * LBM_EINVAL for every < 0 or mass_tol <= 0.
+ */
+int lbm_set_check(lbm_handle* h, int64_t every, double mass_tol);
 
 /* Number of steps taken since lbm_init / lbm_set_state. */
 int64_t lbm_time(const lbm_handle* h);
@@ -285,9 +304,13 @@ size_t lbm_structure_work_bytes(const lbm_handle* h, int32_t k0, int32_t k1, int
 int lbm_structure_functions(lbm_handle* h, int32_t k0, int32_t k1, int32_t q, int32_t r_max,
                             double* work, size_t work_bytes, double* out);
 
-/* Copy the current state to / from a canonical FP64 state (device, 38*N
- * doubles, layout above).  set_state encodes to the handle's storage and
- * resets lbm_time to 0.  Both are asynchronous on the stream. */
+/* Checkpoint and restore (resume a run, or the adjoint's recomputation of a
+ * segment from its checkpoint): copy the current state to / from a canonical
+ * FP64 state (device, 38*N doubles, layout above, caller-owned).  set_state
+ * encodes to the handle's storage (16-bit forms: the rounding residuals of
+ * the moving pairs go to the rest pair, so the stored sums equal the given
+ * ones) and resets lbm_time to 0.  Both are asynchronous on the stream;
+ * LBM_EINVAL for NULL arguments. */
 int lbm_get_state(lbm_handle* h, double* state);
 int lbm_set_state(lbm_handle* h, const double* state);
 

@@ -101,7 +101,12 @@ class HeatFluxObjective(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, rho0, T_d, G, params, n_steps, ckpt_every):
-        p = replace(params, T_d=float(T_d), G=float(G))
+        # T_lat and T0 belong to the scheme, not to the differentiated
+        # parameter: both are pinned at their values for `params` (T_lat left
+        # at 0 would otherwise follow the new T_d through (T_d + T_u)/2 and J
+        # would depend on T_d in a way the adjoint does not differentiate)
+        T_lat = params.T_lat if params.T_lat > 0 else 0.5 * (params.T_d + params.T_u)
+        p = replace(params, T_d=float(T_d), G=float(G), T_lat=T_lat)
         T0 = conduction_profile(params)      # held fixed when T_d varies
         J, drho0, dTd, dG = heat_flux_gradients(p, rho0, n_steps, ckpt_every, T0)
         ctx.save_for_backward(drho0, torch.tensor(dTd, dtype=torch.float64),

@@ -639,6 +639,43 @@ __global__ __launch_bounds__(256) void k_hist(const typename C::S* __restrict__ 
   }
 }
 
+// Numeric guard of lbm_step: per block, the FP64 sums of the stored mass
+// and energy and the number of nodes whose stored populations sum to a
+// non-finite value or to rho <= 0, into partials[blk * 8 + {0, 1, 2}].
+template <typename C, typename R = typename C::R>
+__global__ __launch_bounds__(256) void k_check(const typename C::S* __restrict__ in, DevParams<R> P,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const size_t N = (size_t)P.nx * P.ny * P.nz;
+  double m = 0.0, e = 0.0, bad = 0.0;
+  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+       n += (size_t)gridDim.x * blockDim.x) {
+    typename Codec<C>::T0 f0, g0;
+    Codec<C>::ld0(in, (uint32_t)n, f0, g0);
+    double rho = (double)f0, E = (double)g0;
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+      R f, g;
+      Codec<C>::dec(at32(Codec<C>::row(in, l, N), (uint32_t)n), f, g, P.fref[l], P.gref[l]);
+      rho += (double)f;
+      E += (double)g;
+    }
+    const bool b = !(rho > 0.0) || !isfinite(rho) || !isfinite(E);
+    bad += b ? 1.0 : 0.0;
+    m += b ? 0.0 : rho;
+    e += b ? 0.0 : E;
+  }
+  const double sm = block_sum(m, sh);
+  const double se = block_sum(e, sh);
+  const double sb = block_sum(bad, sh);
+  if (threadIdx.x == 0) {
+    partials[(size_t)blockIdx.x * 8 + 0] = sm;
+    partials[(size_t)blockIdx.x * 8 + 1] = se;
+    partials[(size_t)blockIdx.x * 8 + 2] = sb;
+    for (int q = 3; q < 7; ++q) partials[(size_t)blockIdx.x * 8 + q] = 0.0;
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, size_t n) {
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x)
@@ -1228,6 +1265,9 @@ struct lbm_handle {
   int cur;
   int64_t t;
   int kernel, tile_x, tile_y, z_chunk;
+  int64_t check_every;   // numeric guard interval of lbm_step (0 = off)
+  double check_mass_tol; // relative mass change that counts as a failure
+  double check_mass0;    // stored mass at the first check after init / set_state (0 = not yet)
 };
 
 namespace {
@@ -1708,6 +1748,21 @@ template <typename C> struct SfFn {
     return do_structure<C>(h, k0, k1, q, rmax, w, o);
   }
 };
+template <typename C> struct CheckFn {
+  static int run(lbm_handle* h, double* out) {
+    using R = typename C::R;
+    const DevParams<R> P = dev_params<R>(h->p);
+    const int nblk = std::min(kDiagBlocks, grid_for(h->L.N, 256));
+    hipLaunchKernelGGL((k_check<C>), dim3(nblk), dim3(256), 0, h->stream,
+                       (const typename C::S*)h->buf[h->cur], P, h->partials);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, h->small, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+  }
+};
 template <typename C> struct PworkFn {
   static int run(lbm_handle* h, double* work, double* out) {
     double tot[6];
@@ -1861,9 +1916,34 @@ int lbm_step(lbm_handle* h, int64_t n) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   for (int64_t s = 0; s < n; ++s) {
-    const int rc = dispatch<StepFn>(h->p.storage, h);
+    int rc = dispatch<StepFn>(h->p.storage, h);
     if (rc) return rc;
+    if (h->check_every > 0 && h->t % h->check_every == 0) {
+      double c[3];
+      rc = dispatch<CheckFn>(h->p.storage, h, c);
+      if (rc) return rc;
+      if (c[2] != 0.0)
+        return fail(LBM_ENUMERIC, "step " + std::to_string(h->t) + ": " +
+                                      std::to_string((long long)c[2]) +
+                                      " nodes with non-finite populations or rho <= 0");
+      if (h->check_mass0 == 0.0) {
+        h->check_mass0 = c[0];
+      } else if (!(std::fabs(c[0] / h->check_mass0 - 1.0) <= h->check_mass_tol)) {
+        return fail(LBM_ENUMERIC, "step " + std::to_string(h->t) + ": stored mass changed by " +
+                                      std::to_string(c[0] / h->check_mass0 - 1.0) +
+                                      " (relative)");
+      }
+    }
   }
+  return LBM_OK;
+}
+
+int lbm_set_check(lbm_handle* h, int64_t every, double mass_tol) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (every < 0 || !(mass_tol > 0.0)) return fail(LBM_EINVAL, "need every >= 0 and mass_tol > 0");
+  h->check_every = every;
+  h->check_mass_tol = mass_tol;
+  h->check_mass0 = 0.0;
   return LBM_OK;
 }
 
@@ -1941,7 +2021,10 @@ int lbm_get_state(lbm_handle* h, double* state) {
 int lbm_set_state(lbm_handle* h, const double* state) {
   if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
   const int rc = dispatch<SetFn>(h->p.storage, h, state);
-  if (rc == LBM_OK) h->t = 0;
+  if (rc == LBM_OK) {
+    h->t = 0;
+    h->check_mass0 = 0.0;
+  }
   return rc;
 }
 

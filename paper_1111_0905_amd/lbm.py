@@ -96,6 +96,7 @@ def load_library(path: str = _LIB_PATH):
         "lbm_init": ([P, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.POINTER(H)], ctypes.c_int),
         "lbm_step": ([H, ctypes.c_int64], ctypes.c_int),
+        "lbm_set_check": ([H, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
         "lbm_time": ([H], ctypes.c_int64),
         "lbm_moments": ([H, D, ctypes.c_void_p], ctypes.c_int),
         "lbm_nusselt": ([H, D, D, D, D], ctypes.c_int),
@@ -370,6 +371,11 @@ class Lattice:
 
     def step(self, n: int = 1):
         lbm_step(self.h, n)
+        return self
+
+    def set_check(self, every: int, mass_tol: float = 1e-6):
+        """Numeric guard: lbm_step checks the state every `every` steps."""
+        _check(load_library().lbm_set_check(self.h.h, int(every), float(mass_tol)))
         return self
 
     @property

@@ -236,3 +236,27 @@ def test_autograd_function(glbm):
     assert abs(J.item() - J2) < 1e-15
     assert torch.equal(rho0.grad, dr)
     assert Td.grad.item() == dTd and Gt.grad.item() == dG
+
+
+def test_autograd_function_matches_its_own_finite_differences(glbm):
+    """HeatFluxObjective differentiated against central differences of its
+    own forward in T_d (h = 1e-4 relative), FP64, 8^3, T_lat left at its
+    default: the forward pins T_lat (and T0) at the values of the given
+    parameters, so the derivative the adjoint returns is that of the
+    function's own output."""
+    from paper_1111_0905_amd import adjoint
+    n = 8
+    kw = _kw(tau_nu=1.0, tau_kappa=1.0, gravity=1e-5)
+    p = glbm.Params(n, n, n, storage=glbm.LBM_FP64, **kw)
+    assert p.T_lat == 0.0
+    rho0 = torch.from_numpy(synth.noisy_density(n, n, n, 1.18, 0.01, 3)).cuda().reshape(-1)
+    Gt = torch.tensor(p.G, dtype=torch.float64)
+    Td = torch.tensor(p.T_d, dtype=torch.float64, requires_grad=True)
+    J = adjoint.HeatFluxObjective.apply(rho0, Td, Gt, p, 6, 3)
+    J.backward()
+    h = 1e-4 * p.T_d
+    Jp = adjoint.HeatFluxObjective.apply(rho0, torch.tensor(p.T_d + h, dtype=torch.float64), Gt, p, 6, 3)
+    Jm = adjoint.HeatFluxObjective.apply(rho0, torch.tensor(p.T_d - h, dtype=torch.float64), Gt, p, 6, 3)
+    fd = (Jp.item() - Jm.item()) / (2 * h)
+    print(f"dJ/dT_d adjoint {Td.grad.item():.10e} central difference {fd:.10e}")
+    assert abs(Td.grad.item() - fd) < 1e-4 * abs(fd)

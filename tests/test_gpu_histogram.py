@@ -110,3 +110,46 @@ def test_histogram_on_reduced_storage_counts_every_node(glbm):
         lat.histogram(0, n, glbm.LBM_Q_RHO, (2.0, 0.5), 8)
     with pytest.raises(glbm.LbmError):
         lat.histogram(0, n, 7, (0.5, 2.0), 8)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
+def test_histograms_of_library_stepped_reduced_storage(glbm, storage):
+    """FP32 and FP16-deviation handles stepped by the library (not loaded
+    from the oracle): the joint (rho, T) histogram and the heat-flux pdf
+    against the same binning of the handle's own moment fields (exact up to
+    nodes on bin edges), and those fields against the oracle's within the
+    storage form's bar (1e-5 FP32, 2e-4 FP16)."""
+    nx, ny, nz = 20, 14, 12
+    rho0 = synth.noisy_density(nx, ny, nz, 1.3, 0.3, 77)
+    st = glbm.LBM_FP32 if storage == "fp32" else glbm.LBM_FP16DEV
+    lat = glbm.Lattice(glbm.Params(nx, ny, nz, storage=st, rho_ref=1.3, T_ref=0.9 * TC, **KW),
+                       torch.from_numpy(rho0).cuda())
+    lat.step(40)
+    _, fl = lat.fields()
+    fl = fl.cpu().numpy()
+    o = olbm.Oracle(olbm.Params(nx, ny, nz, **KW), rho0).step(40)
+    m = o.fields()
+    bar = 1e-5 if storage == "fp32" else 2e-4
+    for a, b in ((fl[0], m["rho"].numpy()), (fl[4], m["T"].numpy())):
+        assert np.abs(a - b).max() / np.abs(b).max() < bar
+    k0, k1 = 0, nz
+    rr, tr, nb = (0.2, 2.6), (0.84 * TC, 0.96 * TC), (37, 23)
+    counts, oor, sums = lat.histogram(k0, k1, glbm.LBM_Q_RHO, rr, nb[0], glbm.LBM_Q_T, tr, nb[1])
+    rho, T = fl[0][k0:k1].ravel(), fl[4][k0:k1].ravel()
+    bx, okx, nx_ = _bins(rho, *rr, nb[0])
+    by, oky, ny_ = _bins(T, *tr, nb[1])
+    ok = okx & oky
+    want = np.zeros(nb, dtype=np.int64)
+    np.add.at(want, (bx[ok], by[ok]), 1)
+    got = counts.cpu().numpy()
+    assert np.abs(got - want).sum() <= 2 * int((nx_ | ny_).sum())
+    assert got.sum() + oor == rho.size
+    # heat-flux pdf: rho U v_z with U = c_v T + (G/4) exp(-2/rho)
+    p = olbm.Params(nx, ny, nz, **KW)
+    q = (fl[0] * (p.c_v * fl[4] + 0.25 * p.G * np.exp(-2.0 / fl[0])) * fl[3])[3:9].ravel()
+    lo, hi, n = float(q.min()) * 0.9, float(q.max()) * 0.9, 50
+    counts, oor, sums = lat.histogram(3, 9, glbm.LBM_Q_HEATFLUX, (lo, hi), n)
+    b, okq, near = _bins(q, lo, hi, n)
+    want = np.bincount(b[okq], minlength=n)
+    assert np.abs(counts.cpu().numpy().ravel() - want).sum() <= 2 * int(near.sum())
+    assert abs(sums[1] - q.sum()) < 1e-9 * np.abs(q).sum()

@@ -130,7 +130,7 @@ def test_force_form_coupling_matches_oracle(glbm, storage):
         e_v = float(np.abs(fl[1:4] - of["v"].numpy()).max() / np.abs(of["v"].numpy()).max())
         print(f"FP32 errors: rho {e_rho:.2e} v {e_v:.2e} T {e_T:.2e}")
         assert e_rho < fp32_tolerance() and e_T < fp32_tolerance()
-        assert e_v < 10 * fp32_tolerance()
+        assert e_v < fp32_tolerance()
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
@@ -269,7 +269,78 @@ def test_config1_fp32_fields_match_oracle(glbm):
     e_T = _rel(fl[4], T)
     print(f"FP32 errors: rho {e_rho:.2e} v {e_v:.2e} T {e_T:.2e}")
     assert e_rho < fp32_tolerance() and e_T < fp32_tolerance()
-    assert e_v < 10 * fp32_tolerance()
+    assert e_v < fp32_tolerance()
+
+
+def test_fp32_in_a_roundoff_amplifying_regime(glbm):
+    """The part of this model that amplifies a perturbation within 100 steps.
+    A periodic 32^3 box at T_c = 0.15, 0.8 T_c, the mean of the Maxwell
+    densities, tau = 0.7, no gravity.  Here the velocity of the nearly
+    quiescent fluid (max |v| ~ 7e-6) moves by ~130 times a seeded 1e-7
+    relative perturbation of rho0, relative to its scale.  Density and
+    temperature damp the perturbation.  This holds at every stable
+    parameter set tried, because a density fluctuation compresses
+    adiabatically and phase separation waits for heat diffusion, so a 0.7
+    T_c quench shows no density amplification within 800 steps.
+    The FP32 step must keep rho and T within the plain bar (1e-5).  Its
+    velocity error is set by FP32 rounding of the momentum sums, not by the
+    dynamics: each step rounds every moving population (|f| <= 0.1) by up to
+    2^-24 of itself, so 100 steps allow at most 100 * 2^-24 * 0.1 ~ 6e-7
+    absolute in v."""
+    n = 32
+    Tc = 0.15
+    Gc = eos.coupling_for_tc(Tc)
+    rg, rl, _ = eos.maxwell(0.8 * Tc, Gc)
+    kw = dict(tau_nu=0.7, tau_kappa=0.7, G=Gc, T_d=0.8 * Tc, T_u=0.8 * Tc, T_lat=0.8 * Tc,
+              gravity=0.0, periodic_z=1)
+    print("case: FP32 32^3 amplifying regime, 100 steps", flush=True)
+    rho0 = synth.noisy_density(n, n, n, 0.5 * (rg + rl), 0.01, 1234)
+    u = synth.uniform01(777, n ** 3).reshape(n, n, n)
+    a = _oracle_state(n, n, n, rho0, 100, **kw)
+    b = _oracle_state(n, n, n, rho0 * (1 + 1e-7 * (2 * u - 1)), 100, **kw)
+    fa, fb = a.fields(), b.fields()
+    s = {k: _rel(fb[k].numpy(), fa[k].numpy()) for k in ("rho", "T", "v")}
+    vmax = float(fa["v"].abs().max())
+    print(f"oracle sensitivity to 1e-7: rho {s['rho']:.2e} T {s['T']:.2e} v {s['v']:.2e}"
+          f" (max |v| {vmax:.2e})")
+    assert s["v"] > 1e-6          # the velocity amplifies (the check is not vacuous)
+    lat = _gpu(glbm, n, n, n, rho0, 100, glbm.LBM_FP32, **kw)
+    _, fl = lat.fields()
+    fl = fl.cpu().numpy()
+    e_rho = _rel(fl[0], fa["rho"].numpy())
+    e_T = _rel(fl[4], fa["T"].numpy())
+    dv = float(np.abs(fl[1:4] - fa["v"].numpy()).max())
+    print(f"FP32 errors: rho {e_rho:.2e} T {e_T:.2e} v {dv:.2e} absolute ({dv / vmax:.2e} of max |v|)")
+    assert e_rho < fp32_tolerance() and e_T < fp32_tolerance()
+    assert dv < 100 * 2.0 ** -24 * 0.1
+
+
+@pytest.mark.parametrize("storage", ["fp16dev", "bf16dev"])
+def test_16bit_kernel_variants_agree(glbm, storage):
+    """The register-resident (explicit 64 x 8 tile) and re-reading fused
+    kernels decode the same stored words with the same arithmetic: identical
+    states bit for bit; against the oracle within the packed-storage bar
+    (65 x 9 x 13 ragged, walls, 20 steps).  The pipelined default is held to
+    the same bar."""
+    nx, ny, nz = 65, 9, 13
+    rho_m = _mean_density()
+    rho0 = synth.noisy_density(nx, ny, nz, rho_m, 0.02, 31)
+    kw = _kw(tau_nu=0.8, tau_kappa=0.7, gravity=1e-4)
+    o = _oracle_state(nx, ny, nz, rho0, 20, **kw)
+    st = {"fp16dev": glbm.LBM_FP16DEV, "bf16dev": glbm.LBM_BF16DEV}[storage]
+    states = []
+    for kernel, tx, ty in ((0, 64, 8), (2, 64, 8), (2, 64, 16), (3, 0, 0)):
+        print(f"case: {storage} kernel {kernel} tile {tx}x{ty}", flush=True)
+        lat = _gpu(glbm, nx, ny, nz, rho0, 20, st, kernel=kernel, tile_x=tx, tile_y=ty,
+                   rho_ref=rho_m, T_ref=0.9 * TC, **kw)
+        states.append(lat.state().cpu())
+        _, fl = lat.fields()
+        fl = fl.cpu().numpy()
+        e_rho = _rel(fl[0], o.fields()["rho"].numpy())
+        e_T = _rel(fl[4], o.fields()["T"].numpy())
+        print(f"{storage} kernel {kernel}: rho {e_rho:.2e} T {e_T:.2e}")
+        assert e_rho < PACKED_BARS[storage] and e_T < PACKED_BARS[storage]
+    assert torch.equal(states[0], states[1]) and torch.equal(states[0], states[2])
 
 
 def test_state_roundtrip_and_time(glbm):
@@ -307,3 +378,30 @@ def test_invalid_rho_reports_numeric_error(glbm):
     with pytest.raises(glbm.LbmError) as e:
         lat.moments()
     assert e.value.code == -4
+
+
+def test_numeric_guard_in_step(glbm):
+    """lbm_set_check: a NaN loaded through set_state makes lbm_step return
+    LBM_ENUMERIC at the next check; a mass tolerance below the rounding of
+    FP32 storage trips the mass criterion; a healthy run passes the guard."""
+    nx, ny, nz = 16, 8, 6
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 3)
+    lat = _gpu(glbm, nx, ny, nz, rho0, 0, glbm.LBM_FP32, **_kw())
+    lat.set_check(5, 1e-6)
+    lat.step(20)                                  # healthy: no error
+    s = lat.state()
+    s[:, 2, 3, 4] = float("nan")
+    lat.set_state(s)
+    lat.set_check(3, 1e-6)
+    lib = glbm.load_library()
+    rc = lib.lbm_step(lat.h.h, 3)
+    assert rc == -4, rc
+    assert b"non-finite" in lib.lbm_last_error()
+    # the mass criterion
+    lat2 = _gpu(glbm, nx, ny, nz, rho0, 0, glbm.LBM_FP32, **_kw())
+    lat2.set_check(1, 1e-18)
+    rc = lib.lbm_step(lat2.h.h, 50)
+    assert rc == -4, rc
+    assert b"mass" in lib.lbm_last_error()
+    with pytest.raises(glbm.LbmError):
+        lat2.set_check(-1, 1e-6)
