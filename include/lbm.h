@@ -304,6 +304,22 @@ size_t lbm_structure_work_bytes(const lbm_handle* h, int32_t k0, int32_t k1, int
 int lbm_structure_functions(lbm_handle* h, int32_t k0, int32_t k1, int32_t q, int32_t r_max,
                             double* work, size_t work_bytes, double* out);
 
+/*
+ * lbm_structure_functions without a work buffer, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the field over the planes and the
+ * per-block partial sums go to a static device array of the library, 32 MiB
+ * per GPU (held until the process ends), instead of the caller's work
+ * buffer.  Same arguments, results and errors as lbm_structure_functions
+ * (the same kernels), plus LBM_EWORKSPACE when lbm_structure_work_bytes()
+ * for these planes exceeds 33554432 bytes (e.g. more than about 3.6 million
+ * nodes over the planes).  Allocates nothing, host or device.  Every call on
+ * one GPU uses that GPU's one array, so calls that overlap on one GPU (from
+ * several host threads or streams) race; calls in sequence are safe.
+ */
+int lbm_structure_functions_noalloc(lbm_handle* h, int32_t k0, int32_t k1, int32_t q,
+                                    int32_t r_max, double* out);
+
 /* Checkpoint and restore (resume a run, or the adjoint's recomputation of a
  * segment from its checkpoint): copy the current state to / from a canonical
  * FP64 state (device, 38*N doubles, layout above, caller-owned).  set_state

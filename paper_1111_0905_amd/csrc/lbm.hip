@@ -28,6 +28,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -41,6 +42,16 @@ using namespace lbm;
 namespace {
 
 thread_local std::string g_err;
+
+// Scratch of the allocation-free entry point (lbm_structure_functions_noalloc):
+// one array per GPU the library runs on, held until the process ends.  Host
+// code never uses the array's name as an address: lbm_init takes each
+// device's address once with hipGetSymbolAddress and keeps it per device.
+constexpr size_t kStaticScratchDoubles = (size_t)4 << 20;   // 32 MiB
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -1251,6 +1262,7 @@ Layout layout(const lbm_params* p) {
 struct lbm_handle {
   lbm_params p;
   Layout L;
+  int dev;         // the HIP device current at lbm_init
   hipStream_t stream;
   char* ws;
   void* buf[2];
@@ -1642,8 +1654,8 @@ int do_structure(lbm_handle* h, int k0, int k1, int which, int rmax, double* wor
   hipLaunchKernelGGL(k_finish_increments, dim3(1), dim3(256), 0, h->stream, part, kIncBlocks, rmax,
                      sums);
   HIP_TRY(hipGetLastError());
-  std::vector<double> host(2 * (size_t)rmax);
-  HIP_TRY(hipMemcpyAsync(host.data(), sums, sizeof(double) * 2 * rmax, hipMemcpyDeviceToHost,
+  double host[2 * 256];   // r_max <= 256 (checked by the entry points)
+  HIP_TRY(hipMemcpyAsync(host, sums, sizeof(double) * 2 * rmax, hipMemcpyDeviceToHost,
                          h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   // each separation is counted once per node and direction
@@ -1854,6 +1866,21 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
+  h->dev = dev;
+  {
+    // this device's copy of the static scratch (once per device, with the
+    // device current)
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices && !g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        delete h;
+        return fail(LBM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      }
+      g_scratch_ptr[dev] = (double*)ptr;
+    }
+  }
   h->kernel = p->kernel;
   const int wide_x = p->nx >= 128 ? 128 : (p->nx >= 64 ? 64 : 32);
   if (p->kernel == LBM_KERNEL_PIPELINED) {
@@ -2011,6 +2038,25 @@ int lbm_structure_functions(lbm_handle* h, int32_t k0, int32_t k1, int32_t q, in
   if (work_bytes < lbm_structure_work_bytes(h, k0, k1, r_max))
     return fail(LBM_EWORKSPACE, "work buffer too small (lbm_structure_work_bytes)");
   return dispatch<SfFn>(h->p.storage, h, (int)k0, (int)k1, (int)q, (int)r_max, work, out);
+}
+
+int lbm_structure_functions_noalloc(lbm_handle* h, int32_t k0, int32_t k1, int32_t q,
+                                    int32_t r_max, double* out) {
+  if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (k0 < 0 || k1 > h->p.nz || k0 >= k1) return fail(LBM_EINVAL, "need 0 <= k0 < k1 <= nz");
+  if (q < LBM_Q_RHO || q > LBM_Q_HEATFLUX) return fail(LBM_EINVAL, "unknown quantity");
+  if (r_max < 1 || r_max > 256 || r_max >= h->p.nx || r_max >= h->p.ny)
+    return fail(LBM_EINVAL, "need 1 <= r_max <= 256 and r_max < nx, ny");
+  if ((size_t)std::max(h->p.nx, h->p.ny) * sizeof(double) > 65536)
+    return fail(LBM_EINVAL, "lines longer than 8192 nodes are not supported");
+  const size_t need = lbm_structure_work_bytes(h, k0, k1, r_max);
+  if (need > kStaticScratchDoubles * sizeof(double))
+    return fail(LBM_EWORKSPACE, "planes k0..k1 need " + std::to_string(need) +
+                                    " bytes of scratch, more than the 33554432 bytes of the static "
+                                    "scratch: use lbm_structure_functions with a work buffer");
+  double* ptr = (h->dev >= 0 && h->dev < kMaxDevices) ? g_scratch_ptr[h->dev] : nullptr;
+  if (!ptr) return fail(LBM_EHIP, "no static scratch on the handle's device");
+  return dispatch<SfFn>(h->p.storage, h, (int)k0, (int)k1, (int)q, (int)r_max, ptr, out);
 }
 
 int lbm_get_state(lbm_handle* h, double* state) {

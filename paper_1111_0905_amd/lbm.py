@@ -113,6 +113,8 @@ def load_library(path: str = _LIB_PATH):
                                 ctypes.c_void_p], ctypes.c_int),
         "lbm_structure_work_bytes": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
                                      ctypes.c_size_t),
+        "lbm_structure_functions_noalloc": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, D], ctypes.c_int),
         "lbm_structure_functions": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, D],
                                     ctypes.c_int),
