@@ -1214,7 +1214,8 @@ int validate(const lbm_params* p) {
       return fail(LBM_EINVAL, "the pipelined kernel is built for FP32 and the 16-bit forms only");
     const int tx = p->tile_x, ty = p->tile_y;
     const bool ok = (tx == 0 && ty == 0) || (tx == 32 && (ty == 8 || ty == 16)) ||
-                    (tx == 64 && ty == 8) || (tx == 16 && ty == 16) || (tx == 128 && ty == 4);
+                    (tx == 64 && ty == 8) || (tx == 16 && ty == 16) || (tx == 128 && ty == 4) ||
+                    (tx == 256 && ty == 2);
     if (!ok) return fail(LBM_EINVAL, "unsupported tile shape (tile_x, tile_y) for the pipelined kernel");
   } else {
     const int tx = p->tile_x, ty = p->tile_y;
@@ -1427,6 +1428,7 @@ pipe::PParams pipe_params(const lbm_params& p) {
   auto psi_host = [&](double r) { return p.psi_form ? 1.0 - exp(-r) : exp(-1.0 / r); };
   d.psi_wd = d.wet_d ? (float)psi_host(p.rho_wall_d) : 0.f;
   d.psi_wu = d.wet_u ? (float)psi_host(p.rho_wall_u) : 0.f;
+  d.one = 1.f;
   return d;
 }
 
@@ -1439,6 +1441,7 @@ int with_pipe_tile(int tx, int ty, F&& f) {
   if (tx == 64 && ty == 8) return f(integral_constant<int, 64>{}, integral_constant<int, 8>{});
   if (tx == 16 && ty == 16) return f(integral_constant<int, 16>{}, integral_constant<int, 16>{});
   if (tx == 128 && ty == 4) return f(integral_constant<int, 128>{}, integral_constant<int, 4>{});
+  if (tx == 256 && ty == 2) return f(integral_constant<int, 256>{}, integral_constant<int, 2>{});
   return fail(LBM_EINVAL, "unsupported tile shape for the pipelined kernel");
 }
 

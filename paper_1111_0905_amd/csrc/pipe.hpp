@@ -43,6 +43,8 @@ struct PParams {
   int wet_d, wet_u;
   float psi_wd, psi_wu;
   int psi_form;
+  float one;                // 1.0 (an opaque multiplier: a fused a * one + c of a half
+                            // operand becomes one mixed-precision FMA)
 };
 
 // Stored words: kMove bytes per moving pair; x values are absolute (FP32) or
@@ -57,6 +59,10 @@ template <> struct Word<F32> {
     a = w.x;
     b = w.y;
   }
+  static __device__ __forceinline__ void acc(S w, float, float& sa, float& sb) {
+    sa += w.x;
+    sb += w.y;
+  }
 };
 template <> struct Word<H16> {
   using S = uint32_t;
@@ -67,11 +73,16 @@ template <> struct Word<H16> {
     a = (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
     b = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
   }
-  // encode (a, b); da, db receive the decoded stored values
-  static __device__ __forceinline__ S enc(float a, float b, float& da, float& db) {
+  // sa += lo, sb += hi of a stored word (the conversions fused into the adds)
+  static __device__ __forceinline__ void acc(S w, float one, float& sa, float& sb) {
+    sa = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)), one, sa);
+    sb = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)), one, sb);
+  }
+  // encode (a, b); ra, rb receive the rounding residuals a - stored, b - stored
+  static __device__ __forceinline__ S enc_res(float a, float b, float one, float& ra, float& rb) {
     const _Float16 ha = (_Float16)a, hb = (_Float16)b;
-    da = (float)ha;
-    db = (float)hb;
+    ra = __builtin_fmaf(-(float)ha, one, a);
+    rb = __builtin_fmaf(-(float)hb, one, b);
     return (uint32_t)__builtin_bit_cast(uint16_t, ha) |
            ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
   }
@@ -85,11 +96,22 @@ template <> struct Word<B16> {
     a = __builtin_bit_cast(float, w << 16);
     b = __builtin_bit_cast(float, w & 0xFFFF0000u);
   }
-  static __device__ __forceinline__ S enc(float a, float b, float& da, float& db) {
-    const uint32_t ua = bf16_rne(a), ub = bf16_rne(b);
-    da = __builtin_bit_cast(float, ua << 16);
-    db = __builtin_bit_cast(float, ub << 16);
-    return ua | (ub << 16);
+  static __device__ __forceinline__ void acc(S w, float, float& sa, float& sb) {
+    float a, b;
+    dec(w, a, b);
+    sa += a;
+    sb += b;
+  }
+  // round to nearest even in hardware (the packed conversion of gfx950)
+  static __device__ __forceinline__ S enc_res(float a, float b, float, float& ra, float& rb) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v.x = (__bf16)a;
+    v.y = (__bf16)b;
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    ra = a - __builtin_bit_cast(float, u << 16);
+    rb = b - __builtin_bit_cast(float, u & 0xFFFF0000u);
+    return u;
   }
 };
 
@@ -218,25 +240,37 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
 #pragma unroll
   for (int q = 0; q < 9; ++q) xyb[q] = xyn[q] * W::kMove;
 
-  // ring node of this thread (one per thread, t < nring)
+  // ring nodes of this thread: ring index r = t + m NT for m < NR (NR = 2
+  // when the ring has more nodes than the tile threads, wide flat tiles)
+  constexpr int NR = (2 * (TX + 2) + 2 * TY + NT - 1) / NT;
   const int nring = 2 * (tw + 2) + 2 * th;
-  const bool ringt = t < nring;
-  int rx = 0, ry = 0;
-  if (ringt) {
-    if (t < tw + 2) {
-      rx = t - 1;
-      ry = -1;
-    } else if (t < 2 * (tw + 2)) {
-      rx = t - (tw + 2) - 1;
-      ry = th;
-    } else {
-      const int q = t - 2 * (tw + 2);
-      rx = q < th ? -1 : tw;
-      ry = q < th ? q : q - th;
+  bool ringt[NR];
+  uint32_t ring_n[NR];
+  int ring_s[NR];
+  bool ring_wave[NR];
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    const int r = t + m * NT;
+    ringt[m] = r < nring;
+    int rx = 0, ry = 0;
+    if (ringt[m]) {
+      if (r < tw + 2) {
+        rx = r - 1;
+        ry = -1;
+      } else if (r < 2 * (tw + 2)) {
+        rx = r - (tw + 2) - 1;
+        ry = th;
+      } else {
+        const int q = r - 2 * (tw + 2);
+        rx = q < th ? -1 : tw;
+        ry = q < th ? q : q - th;
+      }
     }
+    ring_n[m] = (uint32_t)wrap(y0 + ry, ny) * nx + (uint32_t)wrap(x0 + rx, nx);
+    ring_s[m] = (ry + 1) * PW + (rx + 1);
+    // ring loads are issued by the waves that hold ring nodes only
+    ring_wave[m] = __builtin_amdgcn_readfirstlane(r) < nring;
   }
-  const uint32_t ring_n = (uint32_t)wrap(y0 + ry, ny) * nx + (uint32_t)wrap(x0 + rx, nx);
-  const int ring_s = (ry + 1) * PW + (rx + 1);
 
   const bool walls = !P.periodic_z;
   auto phys = [&](int kp) { return kp < 0 ? kp + nz : (kp >= nz ? kp - nz : kp); };
@@ -253,22 +287,17 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
       nw.w[l] = BufIO<S>::ld(mkrsrc(row_start(in, row_m, l + (int)W::kRowOff)), vm,
                              (uint32_t)kp * (uint32_t)plane_m);
   };
-  // the ring loads are issued by the waves that hold ring threads only
-  const bool ring_wave = __builtin_amdgcn_readfirstlane(t) < nring;
-  auto load_all = [&](int kp, NodeWords<C>& nw, NodeWords<C>& nr) {
+  auto load_all = [&](int kp, NodeWords<C>& nw, NodeWords<C>* nr) {
     load(kp, xyb[0], xyn[0] * 8u, nw);
-    if (ring_wave) load(kp, ring_n * W::kMove, ring_n * 8u, nr);
+#pragma unroll
+    for (int m = 0; m < NR; ++m)
+      if (ring_wave[m]) load(kp, ring_n[m] * W::kMove, ring_n[m] * 8u, nr[m]);
   };
   // moments (rho, E) of a node's words, in a fixed order
   auto node_moments = [&](const NodeWords<C>& nw, float& rho, float& E) {
     float sf = 0.f, sg = 0.f;
 #pragma unroll
-    for (int l = 1; l < Q; ++l) {
-      float a, b;
-      W::dec(nw.w[l], a, b);
-      sf += a;
-      sg += b;
-    }
+    for (int l = 1; l < Q; ++l) W::acc(nw.w[l], P.one, sf, sg);
     rho = nw.w0.x + (P.Fref + sf);
     E = nw.w0.y + (P.Gref + sg);
   };
@@ -276,17 +305,19 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
     sM[s][q] = make_float4(psi_of<float>(rho, P.psi_form), rho, E, E - P.T_lat * rho);
   };
   // moments of a plane's own and ring nodes into its slot
-  auto fill = [&](int s, const NodeWords<C>& own, const NodeWords<C>& ring) {
+  auto fill = [&](int s, const NodeWords<C>& own, const NodeWords<C>* ring) {
     if (active) {
       float rho, E;
       node_moments(own, rho, E);
       put(s, own_s, rho, E);
     }
-    if (ringt) {
-      float rho, E;
-      node_moments(ring, rho, E);
-      put(s, ring_s, rho, E);
-    }
+#pragma unroll
+    for (int m = 0; m < NR; ++m)
+      if (ringt[m]) {
+        float rho, E;
+        node_moments(ring[m], rho, E);
+        put(s, ring_s[m], rho, E);
+      }
   };
   // wall ghost slot: psi mirrored (or of the prescribed wall density), rho,
   // E and Phi extrapolated linearly through the wall
@@ -351,10 +382,10 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
     auto store = [&](int q, uint32_t so, int xs, float a, float b) {
       const rsrc_t r = mkrsrc(row_start(out, row_m, q + (int)W::kRowOff));
       if constexpr (W::kDev) {
-        float da, db;
-        const S wv = W::enc(a, b, da, db);
-        rf += a - da;
-        rg += b - db;
+        float ra, rb;
+        const S wv = W::enc_res(a, b, P.one, ra, rb);
+        rf += ra;
+        rg += rb;
         BufIO<S>::st(r, xyb[xs], so, wv);
       } else {
         BufIO<S>::st(r, xyb[xs], so, make_float2(a, b));
@@ -406,7 +437,7 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
                       make_float2(nw.w0.x + rf, nw.w0.y + (Ssrc + rg)));
   };
 
-  NodeWords<C> WA, WB, WC, RR;
+  NodeWords<C> WA, WB, WC, RR[NR];
   // prologue: moments of plane k0 - 1 and k0, words of k0 kept, k0 + 1 in flight
   {
     NodeWords<C> tmp;

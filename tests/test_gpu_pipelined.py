@@ -122,7 +122,8 @@ def test_tiles_and_chunks_bit_identical(glbm, storage):
     kw = _kw(tau_nu=0.7, tau_kappa=0.9, gravity=1e-4)
     ref = None
     for tx, ty, zc in [(32, 16, 0), (32, 16, 1), (32, 16, 2), (32, 16, 5), (32, 8, 0),
-                       (64, 8, 3), (16, 16, 0), (16, 16, 4), (32, 16, 23)]:
+                       (64, 8, 3), (16, 16, 0), (16, 16, 4), (32, 16, 23), (128, 4, 0),
+                       (256, 2, 0), (256, 2, 6)]:
         print(f"case: pipelined {storage} tile {tx}x{ty} z_chunk={zc}", flush=True)
         lat = _gpu(glbm, nx, ny, nz, rho0, 7, _storage(glbm, storage), tile_x=tx, tile_y=ty,
                    z_chunk=zc, rho_ref=1.9, T_ref=0.9 * TC, **kw)
