@@ -78,13 +78,19 @@ template <> struct Word<H16> {
     sa = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)), one, sa);
     sb = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)), one, sb);
   }
-  // encode (a, b); ra, rb receive the rounding residuals a - stored, b - stored
+  // encode (a, b) with one packed round-to-nearest-even conversion; ra, rb
+  // receive the rounding residuals a - stored, b - stored (each read back from
+  // its half of the packed word by a mixed-precision FMA)
   static __device__ __forceinline__ S enc_res(float a, float b, float one, float& ra, float& rb) {
-    const _Float16 ha = (_Float16)a, hb = (_Float16)b;
-    ra = __builtin_fmaf(-(float)ha, one, a);
-    rb = __builtin_fmaf(-(float)hb, one, b);
-    return (uint32_t)__builtin_bit_cast(uint16_t, ha) |
-           ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+    typedef float f32x2v __attribute__((ext_vector_type(2)));
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    f32x2v f;
+    f.x = a;
+    f.y = b;
+    const f16x2 h = __builtin_convertvector(f, f16x2);
+    ra = __builtin_fmaf(-(float)h.x, one, a);
+    rb = __builtin_fmaf(-(float)h.y, one, b);
+    return __builtin_bit_cast(uint32_t, h);
   }
 };
 template <> struct Word<B16> {
@@ -114,6 +120,28 @@ template <> struct Word<B16> {
     return u;
   }
 };
+
+// 1/x within one rounding: the hardware reciprocal and one Newton step.
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.f), r, r);
+}
+// e^t from the hardware 2^x, with t log2(e) carried as an unevaluated sum
+// h + l (the FMA gives the product's rounding error exactly) so that the
+// argument adds no error beyond t's own rounding; 2^l = 1 + l ln 2 to far
+// below float precision since |l| < 2^-22.
+__device__ __forceinline__ float exp_f(float t) {
+  const float L = 1.44269502e+00f;    // log2(e) rounded to float
+  const float Ll = 1.92596303e-08f;   // log2(e) - L
+  const float h = t * L;
+  const float l = __builtin_fmaf(t, Ll, __builtin_fmaf(t, L, -h));
+  return __builtin_amdgcn_exp2f(h) * __builtin_fmaf(l, 0.693147181f, 1.f);
+}
+// psi = exp(-1/rho) of eq. (FORCE) (form 0) or the original Shan-Chen 1 - e^-rho
+__device__ __forceinline__ float psi_f(float rho, int form) {
+  const float e = exp_f(form ? -rho : -recip(rho));
+  return form ? 1.f - e : e;
+}
 
 // Index of the x-y offset of direction l among the nine per-thread offsets:
 // 0 node, 1 (+x), 2 (-x), 3 (+y), 4 (-y), 5 (+x+y), 6 (-x-y), 7 (+x-y), 8 (-x+y).
@@ -302,7 +330,7 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
     E = nw.w0.y + (P.Gref + sg);
   };
   auto put = [&](int s, int q, float rho, float E) {
-    sM[s][q] = make_float4(psi_of<float>(rho, P.psi_form), rho, E, E - P.T_lat * rho);
+    sM[s][q] = make_float4(psi_f(rho, P.psi_form), rho, E, E - P.T_lat * rho);
   };
   // moments of a plane's own and ring nodes into its slot
   auto fill = [&](int s, const NodeWords<C>& own, const NodeWords<C>* ring) {
@@ -360,7 +388,7 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
     const float Fx = gp * gpx - gFx;
     const float Fy = gp * gpy - gFy;
     const float Fz = gp * gpz - gFz - P.gravity * rho;
-    const float ir = 1.f / rho;
+    const float ir = recip(rho);
     const float ux = (jx + P.tau_nu * Fx) * ir, uy = (jy + P.tau_nu * Fy) * ir,
                 uz = (jz + P.tau_nu * Fz) * ir;
     const float vx = (jx + 0.5f * Fx) * ir, vy = (jy + 0.5f * Fy) * ir, vz = (jz + 0.5f * Fz) * ir;
