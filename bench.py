@@ -265,7 +265,8 @@ def main():
                          # on 2 x 76 B per node (all 38 populations in 16 bits)
                          "frac_of_peak_152B": round(152 * n ** 3 / (r["ms_per_step"] * 1e-3) / 1e9
                                                     / PEAK_HBM_GBS, 4),
-                         "speedup_vs_fp32": round(r["mlups"] / main_res["mlups"], 3)}
+                         "speedup_vs_fp32": round(r["mlups"] / main_res["mlups"], 3),
+                         "traffic": measured_traffic(st, n)}
     refs = None if args.no_references else bandwidth_references(lbm)
     if refs:
         print(f"bench: copy {refs['copy_gbs']:.0f} GB/s, 19-row pattern {refs['rows19_gbs']:.0f} GB/s",
