@@ -82,7 +82,7 @@ enum {
   LBM_KERNEL_FUSED_RELOAD = 2, /* one z-marching kernel per step, populations re-read from cache */
   LBM_KERNEL_PIPELINED = 3     /* one z-marching kernel per step with the loads of plane k+2 in
                                   flight while plane k collides (FP32 and 16-bit storage only;
-                                  tiles 128 x 4, 64 x 8, 32 x 16, 32 x 8, 16 x 16; 0 x 0 picks
+                                  tiles 128 x 4, 256 x 2, 64 x 8, 32 x 16, 32 x 8, 16 x 16; 0 x 0 picks
                                   the widest 512-thread tile the plane fills) */
 };
 

@@ -1,8 +1,8 @@
 """Parity at full size: the 512^3 boiling convection cell in the launch
 configuration the throughput benchmark times (default kernel, tiles and
 z-chunking for each storage form), and the 128^3 cell (whose default launch
-takes 64 x 8 tiles for FP32 and splits the z columns into chunks: 16 planes for FP32,
-8 for the 16-bit forms).
+runs the pipelined kernel on 128 x 4 tiles and splits the z columns into
+16-plane chunks, so that one round of work-groups covers the lattice).
 
 The oracle cannot step 512^3 nodes, but one node's state after s steps
 depends only on the state within 2 s nodes of it in x and y (the force at a
