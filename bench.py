@@ -88,13 +88,20 @@ def run_storage(lbm, n, storage, steps, warmup, rho0, kernel=0, tile_y=0, z_chun
 
 
 def source_hash():
+    """SHA-256 of the kernel sources' code: comments and blank space are
+    dropped first, so that a change of wording does not disown the counter
+    runs of an unchanged kernel."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_1111_0905_amd", "csrc", "*.hip")) +
                     glob.glob(os.path.join(ROOT, "paper_1111_0905_amd", "csrc", "*.hpp"))):
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

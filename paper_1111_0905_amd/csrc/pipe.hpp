@@ -11,13 +11,15 @@
 //    arithmetic; the words of k+1 (loaded one plane earlier) give the
 //    moments of k+1 and are kept in registers for its collision.  Three word
 //    sets rotate through the roles (collide, next, in flight) by unrolling the
-//    z loop three times, so no register copies are made.  The one-node ring
-//    around the tile is loaded one plane ahead as well (one ring node per
-//    thread) and only its moments are kept.
-//  * Every load and store uses a wave-uniform 64-bit base (population row
-//    plus plane offset, scalar registers) and a per-thread byte offset within
-//    the plane that is fixed for the whole kernel (nine of them: the node and
-//    its eight x-y neighbours, periodic wrap included), so streaming costs no
+//    z loop three times, so no register copies are made.  The words of the
+//    one-node ring around the tile (one ring node per thread, by the waves
+//    that hold ring nodes) are loaded with those of the own node and only
+//    their moments are kept.
+//  * Every load and store is a raw buffer access: the descriptor's base is
+//    the population row (wave-uniform, scalar registers), the scalar offset
+//    the plane, and the vector offset a per-thread byte offset within the
+//    plane that is fixed for the whole kernel (nine of them: the node and its
+//    eight x-y neighbours, periodic wrap included), so streaming costs no
 //    vector address arithmetic.
 //  * rho, psi, E and Phi = E - T_lat rho of a plane and its ring sit in one
 //    float4 per node in an LDS ring of four plane slots (one barrier per
