@@ -1277,6 +1277,8 @@ struct lbm_handle {
   double* aE;
   int cur;
   int64_t t;
+  int64_t state_version;  // bumped whenever buf[cur] changes (init, step, set_state)
+  int64_t rhoE_version;   // the state version srho / sE were computed for
   int kernel, tile_x, tile_y, z_chunk;
   int64_t check_every;   // numeric guard interval of lbm_step (0 = off)
   double check_mass_tol; // relative mass change that counts as a failure
@@ -1492,6 +1494,16 @@ int launch_rhoE(lbm_handle* h, const void* in) {
   return LBM_OK;
 }
 
+// rho and E of the current state in srho / sE, computed once per state
+// (diagnostics of one state share them)
+template <typename C>
+int current_rhoE(lbm_handle* h) {
+  if (h->rhoE_version == h->state_version) return LBM_OK;
+  const int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  if (rc == LBM_OK) h->rhoE_version = h->state_version;
+  return rc;
+}
+
 template <typename C>
 int launch_reference(lbm_handle* h, const void* in, void* out) {
   using R = typename C::R;
@@ -1519,6 +1531,7 @@ int do_step(lbm_handle* h) {
   if (rc) return rc;
   h->cur = 1 - h->cur;
   h->t += 1;
+  ++h->state_version;
   return LBM_OK;
 }
 
@@ -1555,7 +1568,7 @@ int do_set(lbm_handle* h, const double* st) {
 template <typename C>
 int do_moments(lbm_handle* h, double* totals, double* fields) {
   using R = typename C::R;
-  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  int rc = current_rhoE<C>(h);
   if (rc) return rc;
   const DevParams<R> P = dev_params<R>(h->p);
   const int nblk = std::min(kDiagBlocks, grid_for(h->L.N, 256));
@@ -1577,7 +1590,7 @@ int do_moments(lbm_handle* h, double* totals, double* fields) {
 template <typename C>
 int do_nusselt(lbm_handle* h, double* nb, double* nt, double* nu_z, double* T_z) {
   using R = typename C::R;
-  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  int rc = current_rhoE<C>(h);
   if (rc) return rc;
   const DevParams<R> P = dev_params<R>(h->p);
   hipLaunchKernelGGL((k_plane<C>), dim3(h->p.nz), dim3(256), 0, h->stream,
@@ -1610,7 +1623,7 @@ template <typename C>
 int do_hist(lbm_handle* h, const HistSpec& hs, unsigned long long* counts, double* sums,
             uint64_t* out_of_range) {
   using R = typename C::R;
-  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  int rc = current_rhoE<C>(h);
   if (rc) return rc;
   const DevParams<R> P = dev_params<R>(h->p);
   const size_t nbins = (size_t)hs.nxb * hs.nyb;
@@ -1639,7 +1652,7 @@ constexpr int kIncBlocks = 1024;
 template <typename C>
 int do_structure(lbm_handle* h, int k0, int k1, int which, int rmax, double* work, double* out) {
   using R = typename C::R;
-  int rc = launch_rhoE<C>(h, h->buf[h->cur]);
+  int rc = current_rhoE<C>(h);
   if (rc) return rc;
   const DevParams<R> P = dev_params<R>(h->p);
   const int nx = h->p.nx, ny = h->p.ny, planes = k1 - k0;
@@ -1856,6 +1869,8 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->aE = L.adj ? h->gbar + 10 * L.N : nullptr;
   h->cur = 0;
   h->t = 0;
+  h->state_version = 1;
+  h->rhoE_version = 0;
   // defaults from tile/variant sweeps on MI355X (same process, alternating):
   // FP32 and the 16-bit forms use the pipelined kernel on 512-thread tiles
   // as wide as the plane allows (128 x 4: 512^3 FP32 9.14 ms, 256^3 -10 %,
@@ -2070,6 +2085,7 @@ int lbm_get_state(lbm_handle* h, double* state) {
 int lbm_set_state(lbm_handle* h, const double* state) {
   if (!h || !state) return fail(LBM_EINVAL, "NULL argument");
   const int rc = dispatch<SetFn>(h->p.storage, h, state);
+  ++h->state_version;
   if (rc == LBM_OK) {
     h->t = 0;
     h->check_mass0 = 0.0;
