@@ -177,16 +177,13 @@ __device__ __forceinline__ rsrc_t mkrsrc(const char* row) {
   r.w = 0x00020000;                            // gfx9 raw-buffer word 3
   return r;
 }
-#ifndef LBM_PIPE_STORE_AUX
-#define LBM_PIPE_STORE_AUX 0
-#endif
 template <typename T> struct BufIO;
 template <> struct BufIO<uint32_t> {
   static __device__ __forceinline__ uint32_t ld(rsrc_t r, uint32_t v, uint32_t s) {
     return buf_ld_i32(r, (int)v, (int)s, 0);
   }
   static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, uint32_t x) {
-    buf_st_i32(x, r, (int)v, (int)s, LBM_PIPE_STORE_AUX);
+    buf_st_i32(x, r, (int)v, (int)s, 0);
   }
 };
 template <> struct BufIO<float2> {
@@ -198,7 +195,7 @@ template <> struct BufIO<float2> {
     f32x2 u;
     u.x = x.x;
     u.y = x.y;
-    buf_st_v2f32(u, r, (int)v, (int)s, LBM_PIPE_STORE_AUX);
+    buf_st_v2f32(u, r, (int)v, (int)s, 0);
   }
 };
 // Start of row q (row_bytes apart) of a buffer; the empty asm keeps the
