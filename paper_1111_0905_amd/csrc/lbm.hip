@@ -279,6 +279,27 @@ struct ScratchNb {
     const R v1 = a[node_off(ii, jj, ki, nx, ny)];
     return R(2) * v0 - v1;
   }
+  // psi, rho and E of neighbour l at once (one address computation)
+  __device__ __forceinline__ void get3(int l, R& psi, R& rho, R& E) const {
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int ii = wrap(i + CX[l], nx), jj = wrap(j + CY[l], ny);
+    int kk = k + CZ[l];
+    if ((kk >= 0 && kk < nz) || P.periodic_z) {
+      kk = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+      const size_t o = node_off(ii, jj, kk, nx, ny);
+      rho = srho[o];
+      E = sE[o];
+      psi = psi_of<R>(rho, P.psi_form);
+      return;
+    }
+    const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
+    const int ki = kk < 0 ? 1 : nz - 2;     // next plane inside
+    const size_t ow = node_off(ii, jj, kw, nx, ny), oi = node_off(ii, jj, ki, nx, ny);
+    const R r0 = srho[ow];
+    rho = R(2) * r0 - srho[oi];
+    E = R(2) * sE[ow] - sE[oi];
+    psi = (kk < 0 ? P.wet_d : P.wet_u) ? (kk < 0 ? P.psi_wd : P.psi_wu) : psi_of<R>(r0, P.psi_form);
+  }
 };
 
 template <typename R>
@@ -287,9 +308,12 @@ __device__ __forceinline__ Macro<R> macro_from_scratch(const R* f, const R* g, c
   R rho, E;
   moments<R>(f, g, rho, E);
   R gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz;
-  grad_w<R>([&](int l) { return nb.get(0, l); }, gpx, gpy, gpz);
-  grad_w<R>([&](int l) { return nb.get(2, l); }, gEx, gEy, gEz);
-  grad_w<R>([&](int l) { return nb.get(1, l); }, grx, gry, grz);
+  R pn[Q], rn[Q], en[Q];
+#pragma unroll
+  for (int l = 1; l < Q; ++l) nb.get3(l, pn[l], rn[l], en[l]);
+  grad_w<R>([&](int l) { return pn[l]; }, gpx, gpy, gpz);
+  grad_w<R>([&](int l) { return en[l]; }, gEx, gEy, gEz);
+  grad_w<R>([&](int l) { return rn[l]; }, grx, gry, grz);
   return node_macro<R>(f, g, rho, E, psi_of<R>(rho, P.psi_form), gpx, gpy, gpz, gEx, gEy, gEz, grx, gry, grz, P);
 }
 
