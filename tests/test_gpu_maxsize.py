@@ -26,7 +26,8 @@ HALF = 2 * STEPS + 1
 TC = 0.05
 G = eos.coupling_for_tc(TC)
 SEED, AMP = 1234, 0.01
-BARS = {"fp32": (1e-5, 2e-6), "fp16dev": (1e-4, 1e-5), "fp64": (1e-12, 1e-15)}
+BARS = {"fp32": (1e-5, 2e-6), "fp16dev": (1e-4, 1e-5), "bf16dev": (1e-3, 1e-4),
+        "fp64": (1e-12, 1e-15)}
 
 
 def _columns(n):
@@ -76,12 +77,14 @@ def _oracle_columns(n):
     return out
 
 
-@pytest.mark.parametrize("storage,n", [("fp32", 812), ("fp16dev", 812), ("fp64", 645)])
+@pytest.mark.parametrize("storage,n", [("fp32", 812), ("fp16dev", 812), ("bf16dev", 812),
+                                       ("fp64", 645)])
 def test_largest_lattice_sampled_columns(glbm, storage, n):
     print(f"case: {n}^3 {storage}, {STEPS} steps", flush=True)
     oracle_columns = _oracle_columns(n)
     rho_m = _rho_mean()
-    st = {"fp32": glbm.LBM_FP32, "fp16dev": glbm.LBM_FP16DEV, "fp64": glbm.LBM_FP64}[storage]
+    st = {"fp32": glbm.LBM_FP32, "fp16dev": glbm.LBM_FP16DEV, "bf16dev": glbm.LBM_BF16DEV,
+          "fp64": glbm.LBM_FP64}[storage]
     p = glbm.Params(n, n, n, storage=st, rho_ref=rho_m, T_ref=0.9 * TC, **KW)
     rho0 = glbm.lbm_seeded_density(n, n, n, SEED, rho_m, AMP).reshape(-1)
     lat = glbm.Lattice(p, rho0)
