@@ -11,10 +11,11 @@ populations resident in HBM.
 Prints one JSON line: MLUPS, ms per step, the roofline of the step kernel
 (algorithmic bytes = one read and one write of each node's stored
 populations: 2 x 152 B in FP32, 2 x 80 B in the 16-bit forms) against the
-8 TB/s of the data sheet and against two references timed in the same
+8 TB/s of the data sheet and against references timed in the same
 process with the library's plain streaming kernels (a 16-byte-per-lane copy
 of 8 GiB each way, and the step's 19-row read/write pattern without its
-arithmetic), the FP16/BF16-deviation storage forms beside it, and the FP64
+arithmetic, with 400 MiB rows and with the state's own rows), the
+FP16/BF16-deviation storage forms beside it, and the FP64
 CPU oracle timed on a bounded sample on the host.
 """
 import argparse
@@ -118,15 +119,19 @@ def measured_traffic(storage, n):
     return d["traffic_bytes_per_launch"]
 
 
-def bandwidth_references(lbm, gib=8, reps=5):
+def bandwidth_references(lbm, n, gib=8, reps=5):
     """HBM references timed in this process with the library's plain
     streaming kernels: the 16-byte-per-lane copy of `gib` GiB each way (plain
     and non-temporal; the faster counts) and the step's row pattern without
-    arithmetic (19 rows read and written per thread, 400 MiB each, 7.4 GiB
-    each way).  GB/s of reads plus writes."""
+    arithmetic (19 rows read and written per thread), once with rows of 400
+    MiB (7.4 GiB each way) and once per storage form with rows of the n^3
+    state's own moving rows (n^3 x 8 B for FP32, n^3 x 4 B for the 16-bit
+    forms, whose rest row is n^3 x 8 B), the footprint the step streams.
+    GB/s of reads plus writes."""
     import torch
     nbytes = gib << 30
-    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    state_row = {"fp32": n ** 3 * 8, "fp16dev": n ** 3 * 4, "bf16dev": n ** 3 * 4}
+    a = torch.ones(max(nbytes, 19 * max(state_row.values())) // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     stream = torch.cuda.current_stream()
 
@@ -150,10 +155,19 @@ def bandwidth_references(lbm, gib=8, reps=5):
     row = 400 << 20
     ms = timed(lambda: lbm.lbm_stream_rows(a, b, 19, row, row))
     rows19 = 2 * 19 * row / ms / 1e6
+    rows19_state = {}
+    for st, rb in state_row.items():
+        if st == "bf16dev":               # the same rows as fp16dev
+            rows19_state[st] = rows19_state["fp16dev"]
+            continue
+        rb -= rb % 8                       # the row kernel moves 8-byte words
+        ms = timed(lambda: lbm.lbm_stream_rows(a, b, 19, rb, rb))
+        rows19_state[st] = 2 * 19 * rb / ms / 1e6
     del a, b
     torch.cuda.empty_cache()
     return {"copy_gbs": max(copy.values()), "copy_plain_gbs": copy["plain"],
-            "copy_nontemporal_gbs": copy["nontemporal"], "rows19_gbs": rows19}
+            "copy_nontemporal_gbs": copy["nontemporal"], "rows19_gbs": rows19,
+            "rows19_state_gbs": rows19_state}
 
 
 def cpu_baseline(seconds=15.0, n=64, max_steps=None):
@@ -274,12 +288,15 @@ def main():
                                                     / PEAK_HBM_GBS, 4),
                          "speedup_vs_fp32": round(r["mlups"] / main_res["mlups"], 3),
                          "traffic": measured_traffic(st, n)}
-    refs = None if args.no_references else bandwidth_references(lbm)
+    refs = None if args.no_references else bandwidth_references(lbm, n)
     if refs:
-        print(f"bench: copy {refs['copy_gbs']:.0f} GB/s, 19-row pattern {refs['rows19_gbs']:.0f} GB/s",
-              file=sys.stderr, flush=True)
+        rs = refs["rows19_state_gbs"]
+        print(f"bench: copy {refs['copy_gbs']:.0f} GB/s, 19-row pattern {refs['rows19_gbs']:.0f} GB/s "
+              f"(400 MiB rows), {rs['fp32']:.0f} GB/s (FP32 state rows), {rs['fp16dev']:.0f} GB/s "
+              "(16-bit state rows)", file=sys.stderr, flush=True)
         for st, r in extra.items():
             r["frac_of_copy"] = round(r["achieved_gbs"] / refs["copy_gbs"], 4)
+            r["frac_of_rows19_state"] = round(r["achieved_gbs"] / rs[st], 4)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     out = {
@@ -305,7 +322,12 @@ def main():
                      "copy_gbs": round(refs["copy_gbs"], 1) if refs else None,
                      "frac_of_copy": round(main_res["achieved_gbs"] / refs["copy_gbs"], 4) if refs else None,
                      "rows19_gbs": round(refs["rows19_gbs"], 1) if refs else None,
-                     "frac_of_rows19": round(main_res["achieved_gbs"] / refs["rows19_gbs"], 4) if refs else None},
+                     "frac_of_rows19": round(main_res["achieved_gbs"] / refs["rows19_gbs"], 4) if refs else None,
+                     "rows19_state_gbs": round(refs["rows19_state_gbs"][args.storage], 1)
+                     if refs and args.storage in refs["rows19_state_gbs"] else None,
+                     "frac_of_rows19_state": round(main_res["achieved_gbs"]
+                                                   / refs["rows19_state_gbs"][args.storage], 4)
+                     if refs and args.storage in refs["rows19_state_gbs"] else None},
         "bandwidth_references": refs,
         "storage_forms": extra,
         "cpu_baseline": cpu,
