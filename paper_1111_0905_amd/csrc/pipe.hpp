@@ -177,13 +177,25 @@ __device__ __forceinline__ rsrc_t mkrsrc(const char* row) {
   r.w = 0x00020000;                            // gfx9 raw-buffer word 3
   return r;
 }
+// Cache-policy bits of a buffer access (the aux operand): bit 1 marks it
+// non-temporal, so its lines are the first to leave L2.
+constexpr int kNonTemporal = 2;
+// Stores to the x-y slots without an x shift (the node, +y, -y) cover whole
+// 128-byte lines when a row of nx words and a wave's span are whole lines
+// (nx a multiple of 32, tiles of 128 x 4); these are marked non-temporal.
+// An x-shifted store covers part of the line at each end, which a
+// neighbouring wave or tile completes, and stays normal.  The mark is a hint:
+// results do not depend on it.
+__host__ __device__ constexpr bool whole_lines(int xs) { return xs == 0 || xs == 3 || xs == 4; }
+
 template <typename T> struct BufIO;
 template <> struct BufIO<uint32_t> {
   static __device__ __forceinline__ uint32_t ld(rsrc_t r, uint32_t v, uint32_t s) {
     return buf_ld_i32(r, (int)v, (int)s, 0);
   }
+  template <int AUX = 0>
   static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, uint32_t x) {
-    buf_st_i32(x, r, (int)v, (int)s, 0);
+    buf_st_i32(x, r, (int)v, (int)s, AUX);
   }
 };
 template <> struct BufIO<float2> {
@@ -191,11 +203,12 @@ template <> struct BufIO<float2> {
     const f32x2 u = buf_ld_v2f32(r, (int)v, (int)s, 0);
     return make_float2(u.x, u.y);
   }
+  template <int AUX = 0>
   static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float2 x) {
     f32x2 u;
     u.x = x.x;
     u.y = x.y;
-    buf_st_v2f32(u, r, (int)v, (int)s, 0);
+    buf_st_v2f32(u, r, (int)v, (int)s, AUX);
   }
 };
 // Start of row q (row_bytes apart) of a buffer; the empty asm keeps the
@@ -413,9 +426,15 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
         const S wv = W::enc_res(a, b, P.one, ra, rb);
         rf += ra;
         rg += rb;
-        BufIO<S>::st(r, xyb[xs], so, wv);
+        if (whole_lines(xs))
+          BufIO<S>::template st<kNonTemporal>(r, xyb[xs], so, wv);
+        else
+          BufIO<S>::st(r, xyb[xs], so, wv);
       } else {
-        BufIO<S>::st(r, xyb[xs], so, make_float2(a, b));
+        if (whole_lines(xs))
+          BufIO<S>::template st<kNonTemporal>(r, xyb[xs], so, make_float2(a, b));
+        else
+          BufIO<S>::st(r, xyb[xs], so, make_float2(a, b));
       }
     };
 #pragma unroll
@@ -460,7 +479,8 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
       }
     }
     // rest pair, remainder form: mass kept, energy + S
-    BufIO<float2>::st(mkrsrc(row_start(out, row_m, 0)), xyn[0] * 8u, (uint32_t)k * (uint32_t)plane_0,
+    BufIO<float2>::template st<kNonTemporal>(mkrsrc(row_start(out, row_m, 0)), xyn[0] * 8u,
+                      (uint32_t)k * (uint32_t)plane_0,
                       make_float2(nw.w0.x + rf, nw.w0.y + (Ssrc + rg)));
   };
 
