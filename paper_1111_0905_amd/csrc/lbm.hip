@@ -1270,7 +1270,8 @@ struct Layout {
 Layout layout(const lbm_params* p) {
   Layout L;
   L.N = (size_t)p->nx * p->ny * p->nz;
-  L.pop_bytes = align_up(L.N * node_bytes(p->storage));
+  // node_bytes = the words of one node in all its rows; rows are row_pitch(N) apart
+  L.pop_bytes = align_up(row_pitch(L.N) * node_bytes(p->storage));
   L.buf = L.pop_bytes;
   L.scr = align_up(L.N * real_bytes(p->storage));
   L.part = align_up((size_t)kDiagBlocks * 8 * sizeof(double));

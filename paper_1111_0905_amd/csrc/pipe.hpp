@@ -243,7 +243,7 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
   const size_t N = (size_t)A * (size_t)nz;
   // bytes of one plane of a moving row / of the rest row, and the row starts
   const size_t plane_m = (size_t)A * W::kMove, plane_0 = (size_t)A * 8u;
-  const size_t row_m = N * W::kMove;
+  const size_t row_m = row_pitch(N) * W::kMove;
 
   // XCD-aware tile order (work-groups are dealt round-robin over 8 XCDs)
   int bid = blockIdx.x;
