@@ -126,12 +126,17 @@ def bandwidth_references(lbm, n, gib=8, reps=5):
     arithmetic (19 rows read and written per thread), once with rows of 400
     MiB (7.4 GiB each way) and once per storage form with rows of the n^3
     state's own moving rows (n^3 x 8 B for FP32, n^3 x 4 B for the 16-bit
-    forms, whose rest row is n^3 x 8 B), the footprint the step streams.
+    forms, whose rest row is n^3 x 8 B) at the state's row pitch, the
+    footprint the step streams.
     GB/s of reads plus writes."""
     import torch
     nbytes = gib << 30
     state_row = {"fp32": n ** 3 * 8, "fp16dev": n ** 3 * 4, "bf16dev": n ** 3 * 4}
-    a = torch.ones(max(nbytes, 19 * max(state_row.values())) // 4, dtype=torch.float32, device="cuda")
+    # rows of the state lie row_pitch words apart (the node count rounded up to
+    # 16384, plus 1024: the library's layout)
+    pitch = -(-n ** 3 // 16384) * 16384 + 1024
+    state_stride = {"fp32": pitch * 8, "fp16dev": pitch * 4, "bf16dev": pitch * 4}
+    a = torch.ones(max(nbytes, 19 * max(state_stride.values())) // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     stream = torch.cuda.current_stream()
 
@@ -161,7 +166,7 @@ def bandwidth_references(lbm, n, gib=8, reps=5):
             rows19_state[st] = rows19_state["fp16dev"]
             continue
         rb -= rb % 8                       # the row kernel moves 8-byte words
-        ms = timed(lambda: lbm.lbm_stream_rows(a, b, 19, rb, rb))
+        ms = timed(lambda: lbm.lbm_stream_rows(a, b, 19, state_stride[st], rb))
         rows19_state[st] = 2 * 19 * rb / ms / 1e6
     del a, b
     torch.cuda.empty_cache()
