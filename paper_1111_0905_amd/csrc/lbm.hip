@@ -234,7 +234,7 @@ __global__ void k_set_state(typename C::S* out, const double* __restrict__ st, D
 // rho and E of every node into scratch.
 template <typename C, typename R = typename C::R>
 __global__ void k_rhoE(const typename C::S* __restrict__ in, R* __restrict__ srho,
-                       R* __restrict__ sE, DevParams<R> P) {
+                       R* __restrict__ sE, R* __restrict__ spsi, DevParams<R> P) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
@@ -244,18 +244,21 @@ __global__ void k_rhoE(const typename C::S* __restrict__ in, R* __restrict__ srh
     moments<R>(f, g, rho, E);
     srho[n] = rho;
     sE[n] = E;
+    spsi[n] = psi_of<R>(rho, P.psi_form);
   }
 }
 
 // Neighbour values from scratch with the wall ghosts: psi from the mirrored
 // density (or the prescribed wall density), rho and E extrapolated linearly
-// through the wall.
+// through the wall.  spsi: psi of every node (written with rho and E), or
+// NULL to evaluate psi from rho here.
 template <typename R>
 struct ScratchNb {
   const R* srho;
   const R* sE;
   const DevParams<R>& P;
   int i, j, k;
+  const R* spsi = nullptr;
   // which: 0 = psi, 1 = rho, 2 = E
   __device__ __forceinline__ R get(int which, int l) const {
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -263,17 +266,22 @@ struct ScratchNb {
     int kk = k + CZ[l];
     const R* a = which == 2 ? sE : srho;
     if (kk >= 0 && kk < nz) {
-      const R v = a[node_off(ii, jj, kk, nx, ny)];
+      const uint32_t o = node_off(ii, jj, kk, nx, ny);
+      if (which == 0 && spsi) return spsi[o];
+      const R v = a[o];
       return which == 0 ? psi_of<R>(v, P.psi_form) : v;
     }
     if (P.periodic_z) {
       kk = kk < 0 ? kk + nz : kk - nz;
-      const R v = a[node_off(ii, jj, kk, nx, ny)];
+      const uint32_t o = node_off(ii, jj, kk, nx, ny);
+      if (which == 0 && spsi) return spsi[o];
+      const R v = a[o];
       return which == 0 ? psi_of<R>(v, P.psi_form) : v;
     }
     const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
     const int ki = kk < 0 ? 1 : nz - 2;     // next plane inside
     if (which == 0 && (kk < 0 ? P.wet_d : P.wet_u)) return kk < 0 ? P.psi_wd : P.psi_wu;
+    if (which == 0 && spsi) return spsi[node_off(ii, jj, kw, nx, ny)];
     const R v0 = a[node_off(ii, jj, kw, nx, ny)];
     if (which == 0) return psi_of<R>(v0, P.psi_form);
     const R v1 = a[node_off(ii, jj, ki, nx, ny)];
@@ -289,7 +297,7 @@ struct ScratchNb {
       const size_t o = node_off(ii, jj, kk, nx, ny);
       rho = srho[o];
       E = sE[o];
-      psi = psi_of<R>(rho, P.psi_form);
+      psi = spsi ? spsi[o] : psi_of<R>(rho, P.psi_form);
       return;
     }
     const int kw = kk < 0 ? 0 : nz - 1;     // wall plane
@@ -298,7 +306,8 @@ struct ScratchNb {
     const R r0 = srho[ow];
     rho = R(2) * r0 - srho[oi];
     E = R(2) * sE[ow] - sE[oi];
-    psi = (kk < 0 ? P.wet_d : P.wet_u) ? (kk < 0 ? P.psi_wd : P.psi_wu) : psi_of<R>(r0, P.psi_form);
+    psi = (kk < 0 ? P.wet_d : P.wet_u) ? (kk < 0 ? P.psi_wd : P.psi_wu)
+                                       : (spsi ? spsi[ow] : psi_of<R>(r0, P.psi_form));
   }
 };
 
@@ -319,7 +328,8 @@ __device__ __forceinline__ Macro<R> macro_from_scratch(const R* f, const R* g, c
 
 template <typename C, typename R = typename C::R>
 __global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* __restrict__ out,
-                          const R* __restrict__ srho, const R* __restrict__ sE, DevParams<R> P) {
+                          const R* __restrict__ srho, const R* __restrict__ sE,
+                          const R* __restrict__ spsi, DevParams<R> P) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
        n += (size_t)gridDim.x * blockDim.x) {
@@ -328,7 +338,7 @@ __global__ void k_collide(const typename C::S* __restrict__ in, typename C::S* _
     const int k = (int)(n / ((size_t)P.nx * P.ny));
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
-    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    ScratchNb<R> nb{srho, sE, P, i, j, k, spsi};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
     Streamer<C> em{out, in, P, N, i, j, k, wrap(i - 1, P.nx), wrap(i + 1, P.nx),
                    wrap(j - 1, P.ny), wrap(j + 1, P.ny)};
@@ -539,20 +549,23 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 template <typename C, typename R = typename C::R>
 __global__ __launch_bounds__(256) void k_diag(const typename C::S* __restrict__ in,
                                               const R* __restrict__ srho, const R* __restrict__ sE,
+                                              const R* __restrict__ spsi,
                                               DevParams<R> P, double c_v, double G,
                                               double* __restrict__ fields,
                                               double* __restrict__ partials) {
   __shared__ double sh[4];
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
-       n += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % P.nx);
-    const int j = (int)((n / P.nx) % P.ny);
-    const int k = (int)(n / ((size_t)P.nx * P.ny));
+  // node indices fit 32 bits (every population row stays below 4 GiB)
+  const uint32_t N32 = (uint32_t)N, nx = (uint32_t)P.nx, ny = (uint32_t)P.ny;
+  for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < N32; n += gridDim.x * blockDim.x) {
+    const uint32_t r = n / nx;
+    const int i = (int)(n - r * nx);
+    const int j = (int)(r % ny);
+    const int k = (int)(r / ny);
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
-    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    ScratchNb<R> nb{srho, sE, P, i, j, k, spsi};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
     // mass and energy sums of the stored populations in FP64 (the FP32 node
     // sums of the compute path round the same way at nodes of equal state,
@@ -605,6 +618,7 @@ constexpr int kLdsBins = 16384;
 template <typename C, typename R = typename C::R>
 __global__ __launch_bounds__(256) void k_hist(const typename C::S* __restrict__ in,
                                               const R* __restrict__ srho, const R* __restrict__ sE,
+                                              const R* __restrict__ spsi,
                                               DevParams<R> P, double c_v, double G, HistSpec hs,
                                               unsigned long long* __restrict__ counts,
                                               double* __restrict__ partials) {
@@ -618,14 +632,17 @@ __global__ __launch_bounds__(256) void k_hist(const typename C::S* __restrict__ 
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   const size_t A = (size_t)P.nx * P.ny;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (size_t n = (size_t)hs.k0 * A + blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-       n < (size_t)hs.k1 * A; n += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % P.nx);
-    const int j = (int)((n / P.nx) % P.ny);
-    const int k = (int)(n / A);
+  // node indices fit 32 bits (every population row stays below 4 GiB)
+  const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny;
+  for (uint32_t n = (uint32_t)(hs.k0 * A) + blockIdx.x * blockDim.x + threadIdx.x;
+       n < (uint32_t)(hs.k1 * A); n += gridDim.x * blockDim.x) {
+    const uint32_t r = n / nx;
+    const int i = (int)(n - r * nx);
+    const int j = (int)(r % ny);
+    const int k = (int)(r / ny);
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
-    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    ScratchNb<R> nb{srho, sE, P, i, j, k, spsi};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
     typename Codec<C>::T0 f0, g0;
     Codec<C>::ld0(in, (uint32_t)n, f0, g0);
@@ -722,7 +739,8 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
 template <typename C, typename R = typename C::R>
 __global__ __launch_bounds__(256) void k_quantity(const typename C::S* __restrict__ in,
                                                   const R* __restrict__ srho,
-                                                  const R* __restrict__ sE, DevParams<R> P,
+                                                  const R* __restrict__ sE,
+                                                  const R* __restrict__ spsi, DevParams<R> P,
                                                   double c_v, double G, int k0, int k1, int which,
                                                   double* __restrict__ q) {
   const size_t N = (size_t)P.nx * P.ny * P.nz;
@@ -734,7 +752,7 @@ __global__ __launch_bounds__(256) void k_quantity(const typename C::S* __restric
     const int k = (int)(n / A);
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
-    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    ScratchNb<R> nb{srho, sE, P, i, j, k, spsi};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
     typename Codec<C>::T0 f0, g0;
     Codec<C>::ld0(in, (uint32_t)n, f0, g0);
@@ -830,19 +848,23 @@ __global__ __launch_bounds__(256) void k_finish_totals(const double* __restrict_
 template <typename C, typename R = typename C::R>
 __global__ __launch_bounds__(256) void k_plane(const typename C::S* __restrict__ in,
                                                const R* __restrict__ srho, const R* __restrict__ sE,
-                                               DevParams<R> P, double c_v, double G,
-                                               double* __restrict__ prof) {
+                                               const R* __restrict__ spsi,
+                                               DevParams<R> P, double c_v, double G, int S,
+                                               double* __restrict__ out) {
   __shared__ double sh[4];
-  const int k = blockIdx.x;
+  // S blocks per plane: block b = k S + s sums nodes s blockDim + t, stepping
+  // S blockDim; with S = 1 it writes the plane's averages to out[2 k], else
+  // its two sums to out[2 b] (k_plane_sum adds the slices in order)
+  const int k = blockIdx.x / S, sl = blockIdx.x - k * S;
   const size_t N = (size_t)P.nx * P.ny * P.nz;
   const int plane = P.nx * P.ny;
   double sT = 0.0, sF = 0.0;
-  for (int q = threadIdx.x; q < plane; q += blockDim.x) {
+  for (int q = sl * blockDim.x + threadIdx.x; q < plane; q += S * blockDim.x) {
     const int i = q % P.nx, j = q / P.nx;
     const uint32_t n = node_off(i, j, k, P.nx, P.ny);
     R f[Q], g[Q];
     load_node<C>(in, N, (uint32_t)n, P, f, g);
-    ScratchNb<R> nb{srho, sE, P, i, j, k};
+    ScratchNb<R> nb{srho, sE, P, i, j, k, spsi};
     const Macro<R> m = macro_from_scratch<R>(f, g, nb, P);
     const double rho = m.rho, T = m.T;
     const double U = c_v * T + 0.25 * G * exp(-2.0 / rho);
@@ -852,6 +874,25 @@ __global__ __launch_bounds__(256) void k_plane(const typename C::S* __restrict__
   const double a = block_sum(sT, sh);
   const double b = block_sum(sF, sh);
   if (threadIdx.x == 0) {
+    if (S == 1) {
+      out[2 * k] = a / plane;
+      out[2 * k + 1] = b / plane;
+    } else {
+      out[2 * blockIdx.x] = a;
+      out[2 * blockIdx.x + 1] = b;
+    }
+  }
+}
+
+// plane averages from the S slice sums of each plane, added in slice order
+__global__ void k_plane_sum(const double* __restrict__ part, int S, int nz, int plane,
+                            double* __restrict__ prof) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nz; k += gridDim.x * blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int sl = 0; sl < S; ++sl) {
+      a += part[2 * (k * S + sl)];
+      b += part[2 * (k * S + sl) + 1];
+    }
     prof[2 * k] = a / plane;
     prof[2 * k + 1] = b / plane;
   }
@@ -1279,7 +1320,7 @@ Layout layout(const lbm_params* p) {
   // adjoint scratch, FP64 for every storage form: 9 gradient-adjoint
   // components plus rho and E of the forward state
   L.adj = p->adjoint ? align_up((size_t)11 * L.N * sizeof(double)) : 0;
-  L.total = 2 * L.buf + 2 * L.scr + L.part + 2 * L.small + L.adj;
+  L.total = 2 * L.buf + 3 * L.scr + L.part + 2 * L.small + L.adj;
   return L;
 }
 
@@ -1294,6 +1335,7 @@ struct lbm_handle {
   void* buf[2];
   void* srho;
   void* sE;
+  void* spsi;      // psi of the state in srho (written with it)
   double* partials;
   double* small;   // totals / nusselt results
   double* prof;    // plane profiles (2 nz)
@@ -1514,7 +1556,7 @@ int launch_rhoE(lbm_handle* h, const void* in) {
   using R = typename C::R;
   const DevParams<R> P = dev_params<R>(h->p);
   hipLaunchKernelGGL((k_rhoE<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
-                     (const typename C::S*)in, (R*)h->srho, (R*)h->sE, P);
+                     (const typename C::S*)in, (R*)h->srho, (R*)h->sE, (R*)h->spsi, P);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -1537,7 +1579,7 @@ int launch_reference(lbm_handle* h, const void* in, void* out) {
   const DevParams<R> P = dev_params<R>(h->p);
   hipLaunchKernelGGL((k_collide<C>), dim3(grid_for(h->L.N, 256)), dim3(256), 0, h->stream,
                      (const typename C::S*)in, (typename C::S*)out, (const R*)h->srho,
-                     (const R*)h->sE, P);
+                     (const R*)h->sE, (const R*)h->spsi, P);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -1598,7 +1640,8 @@ int do_moments(lbm_handle* h, double* totals, double* fields) {
   const DevParams<R> P = dev_params<R>(h->p);
   const int nblk = std::min(kDiagBlocks, grid_for(h->L.N, 256));
   hipLaunchKernelGGL((k_diag<C>), dim3(nblk), dim3(256), 0, h->stream,
-                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE,
+                     (const R*)h->spsi, P,
                      h->p.c_v, h->p.G, fields, h->partials);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
@@ -1618,15 +1661,28 @@ int do_nusselt(lbm_handle* h, double* nb, double* nt, double* nu_z, double* T_z)
   int rc = current_rhoE<C>(h);
   if (rc) return rc;
   const DevParams<R> P = dev_params<R>(h->p);
-  hipLaunchKernelGGL((k_plane<C>), dim3(h->p.nz), dim3(256), 0, h->stream,
-                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
-                     h->p.c_v, h->p.G, h->prof);
+  // slices per plane: about 1536 work-groups in all (two rounds of three
+  // 256-thread groups per CU on 256 CUs), no more slices than 256-node
+  // strips of a plane, and the slice sums must fit the partials buffer;
+  // the count depends on the shape only, so the sums' order does too
+  const int nz = h->p.nz, plane = h->p.nx * h->p.ny;
+  int S = 1;
+  if (2LL * nz <= 8LL * kDiagBlocks)
+    S = std::max(1, std::min({(1536 + nz - 1) / nz, (plane + 255) / 256, (4 * kDiagBlocks) / nz}));
+  hipLaunchKernelGGL((k_plane<C>), dim3(nz * S), dim3(256), 0, h->stream,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE,
+                     (const R*)h->spsi, P,
+                     h->p.c_v, h->p.G, S, S == 1 ? h->prof : h->partials);
   HIP_TRY(hipGetLastError());
+  if (S > 1) {
+    hipLaunchKernelGGL(k_plane_sum, dim3(grid_for(nz, 256)), dim3(256), 0, h->stream, h->partials, S,
+                       nz, plane, h->prof);
+    HIP_TRY(hipGetLastError());
+  }
   const double kappa = h->p.c_v * (h->p.tau_kappa - 0.5) * h->p.rho_kappa / 3.0;
   hipLaunchKernelGGL(k_finish_nusselt, dim3(1), dim3(256), 0, h->stream, h->prof, h->p.nz,
                      h->p.T_d, h->p.T_u, kappa, h->small);
   HIP_TRY(hipGetLastError());
-  const int nz = h->p.nz;
   double* host = (double*)malloc(sizeof(double) * (2 + 2 * (size_t)nz));
   if (!host) return fail(LBM_EINVAL, "host allocation failed");
   hipError_t e = hipMemcpyAsync(host, h->small, sizeof(double) * (2 + 2 * (size_t)nz),
@@ -1658,7 +1714,8 @@ int do_hist(lbm_handle* h, const HistSpec& hs, unsigned long long* counts, doubl
   const int nblk = std::max(1, std::min(kDiagBlocks, grid_for(nodes, 256)));
   const size_t lds = nbins <= (size_t)kLdsBins ? nbins * sizeof(uint32_t) : 0;
   hipLaunchKernelGGL((k_hist<C>), dim3(nblk), dim3(256), lds, h->stream,
-                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE, P,
+                     (const typename C::S*)h->buf[h->cur], (const R*)h->srho, (const R*)h->sE,
+                     (const R*)h->spsi, P,
                      h->p.c_v, h->p.G, hs, counts, h->partials);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_finish_totals, dim3(1), dim3(256), 0, h->stream, h->partials, nblk, h->small);
@@ -1684,7 +1741,7 @@ int do_structure(lbm_handle* h, int k0, int k1, int which, int rmax, double* wor
   const size_t nodes = (size_t)planes * nx * ny;
   hipLaunchKernelGGL((k_quantity<C>), dim3(std::min(kDiagBlocks, grid_for(nodes, 256))), dim3(256),
                      0, h->stream, (const typename C::S*)h->buf[h->cur], (const R*)h->srho,
-                     (const R*)h->sE, P, h->p.c_v, h->p.G, k0, k1, which, work);
+                     (const R*)h->sE, (const R*)h->spsi, P, h->p.c_v, h->p.G, k0, k1, which, work);
   HIP_TRY(hipGetLastError());
   double* part = work + nodes;
   double* sums = part + (size_t)kIncBlocks * rmax * 2;
@@ -1886,6 +1943,7 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   h->buf[1] = c; c += L.buf;
   h->srho = c; c += L.scr;
   h->sE = c; c += L.scr;
+  h->spsi = c; c += L.scr;
   h->partials = (double*)c; c += L.part;
   h->small = (double*)c; c += L.small;
   h->prof = (double*)c; c += L.small;
