@@ -369,9 +369,7 @@ __global__ __launch_bounds__(TX * TY) void k_fused(const typename C::S* __restri
 
   // XCD-aware tile order: consecutive tiles land on the same XCD (work-groups
   // are dealt round-robin over the 8 XCDs), so neighbouring tiles share L2.
-  int bid = blockIdx.x;
-  const int nb = gridDim.x;
-  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = bid % ntx;
   const int rem = bid / ntx;
   const int ty = rem % nty;
@@ -2010,11 +2008,13 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
   if (p->z_chunk) {
     h->z_chunk = std::min(p->z_chunk, p->nz);
   } else {
-    // split the z columns until the launch has as many work-groups as the
-    // GPU holds at once (compute units x work-groups per unit for this
-    // kernel), so that one wave of work-groups covers the lattice; every
-    // chunk re-reads one halo plane on each side, so chunks stay at least 4
-    // planes deep
+    // split the z columns into the number of chunks that makes the launch
+    // shortest: its rounds of resident work-groups (compute units x
+    // work-groups per unit for this kernel) times the planes each work-group
+    // marches (its chunk and the halo plane it re-reads on each side).  One
+    // chunk when the tiles fill whole rounds; a split when one round would
+    // not fill the GPU or the last round would run nearly empty.  Chunks stay
+    // at least 4 planes deep; ties go to fewer chunks.
     const long long tiles = (long long)((p->nx + h->tile_x - 1) / h->tile_x) *
                             ((p->ny + h->tile_y - 1) / h->tile_y);
     int per_cu = h->kernel == LBM_KERNEL_REFERENCE
@@ -2022,10 +2022,20 @@ int lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const
                      : dispatch<OccupancyFn>(p->storage, h->kernel, h->tile_x, h->tile_y);
     if (per_cu < 1) per_cu = 1;
     const long long want = (long long)cus * per_cu;
-    const long long nzc = std::max(1LL, (want + tiles - 1) / tiles);
-    int zc = (int)((p->nz + nzc - 1) / nzc);
-    zc = std::max(zc, 4);
-    h->z_chunk = std::min(zc, p->nz);
+    int zc_best = p->nz;
+    long long cost_best = -1;
+    for (int c = 1; c <= p->nz; ++c) {
+      const int zc = (p->nz + c - 1) / c;
+      if (c > 1 && zc < 4) break;
+      if (c > 1 && zc == (p->nz + c - 2) / (c - 1)) continue;   // same chunks as c - 1
+      const long long chunks = (p->nz + zc - 1) / zc;
+      const long long cost = (tiles * chunks + want - 1) / want * (zc + 2);
+      if (cost_best < 0 || cost < cost_best) {
+        cost_best = cost;
+        zc_best = zc;
+      }
+    }
+    h->z_chunk = std::min(zc_best, p->nz);
   }
   rc = dispatch<InitFn>(p->storage, h, rho0, T0);
   if (rc == LBM_OK) {

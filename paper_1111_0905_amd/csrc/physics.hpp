@@ -133,6 +133,15 @@ __host__ __device__ constexpr size_t row_pitch(size_t N) {
   return ((N + 16383) & ~(size_t)16383) + 1024;
 }
 
+// Tile of work-group b of nb.  Work-groups are dealt round-robin over the 8
+// XCDs (b on XCD b mod 8); XCD x takes a contiguous range of tiles (the first
+// nb mod 8 XCDs one tile more than the others), so that neighbouring tiles
+// share an L2.  A bijection of [0, nb) for every nb.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Per storage form: enc/dec of one moving pair word, the row of direction
 // l >= 1 (rows row_pitch(N) words apart), and the rest pair (type T0).  kRemainder: the rest pair is updated
 // in remainder form (FP32 and the 16-bit forms); kResidual: the moving stores

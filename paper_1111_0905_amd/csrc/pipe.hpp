@@ -246,9 +246,7 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
   const size_t row_m = row_pitch(N) * W::kMove;
 
   // XCD-aware tile order (work-groups are dealt round-robin over 8 XCDs)
-  int bid = blockIdx.x;
-  const int nb = gridDim.x;
-  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = bid % ntx;
   const int rem = bid / ntx;
   const int ty = rem % nty;
