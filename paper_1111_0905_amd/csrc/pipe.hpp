@@ -30,8 +30,10 @@
 //    (rho_ref, T_ref) (f_ref,l = 3 w_l rho_ref T_lat, g_ref,l = w_l rho_kappa
 //    T_ref for l >= 1), so decoding is a conversion and the equilibria carry
 //    the reference in their node constants.  The rest pair is FP32 and is
-//    updated in remainder form (old value plus what the moving pairs lost,
-//    including the rounding of their 16-bit stores).
+//    updated in remainder form: old value plus what the moving pairs lost.
+//    In the 16-bit forms that is the sum over the 18 words of old decoded
+//    value minus stored value (collision change and store rounding at once,
+//    each difference of two halves exact), plus the wall's change to g.
 
 namespace pipe {
 
@@ -80,18 +82,20 @@ template <> struct Word<H16> {
     sa = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)), one, sa);
     sb = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)), one, sb);
   }
-  // encode (a, b) with one packed round-to-nearest-even conversion; ra, rb
-  // receive the rounding residuals a - stored, b - stored (each read back from
-  // its half of the packed word by a mixed-precision FMA)
-  static __device__ __forceinline__ S enc_res(float a, float b, float one, float& ra, float& rb) {
+  // encode (a, b) with one packed round-to-nearest-even conversion; da, db
+  // receive xa - stored and xb - stored, each stored half read back by a
+  // mixed-precision FMA (the difference of two halves is exact in FP32 unless
+  // their exponents lie more than 13 apart)
+  static __device__ __forceinline__ S enc_diff(float a, float b, float one, float xa, float xb,
+                                               float& da, float& db) {
     typedef float f32x2v __attribute__((ext_vector_type(2)));
     typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
     f32x2v f;
     f.x = a;
     f.y = b;
     const f16x2 h = __builtin_convertvector(f, f16x2);
-    ra = __builtin_fmaf(-(float)h.x, one, a);
-    rb = __builtin_fmaf(-(float)h.y, one, b);
+    da = __builtin_fmaf(-(float)h.x, one, xa);
+    db = __builtin_fmaf(-(float)h.y, one, xb);
     return __builtin_bit_cast(uint32_t, h);
   }
 };
@@ -110,15 +114,17 @@ template <> struct Word<B16> {
     sa += a;
     sb += b;
   }
-  // round to nearest even in hardware (the packed conversion of gfx950)
-  static __device__ __forceinline__ S enc_res(float a, float b, float, float& ra, float& rb) {
+  // round to nearest even in hardware (the packed conversion of gfx950); da,
+  // db as for H16
+  static __device__ __forceinline__ S enc_diff(float a, float b, float, float xa, float xb,
+                                               float& da, float& db) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     bf16x2 v;
     v.x = (__bf16)a;
     v.y = (__bf16)b;
     const uint32_t u = __builtin_bit_cast(uint32_t, v);
-    ra = a - __builtin_bit_cast(float, u << 16);
-    rb = b - __builtin_bit_cast(float, u & 0xFFFF0000u);
+    da = xa - __builtin_bit_cast(float, u << 16);
+    db = xb - __builtin_bit_cast(float, u & 0xFFFF0000u);
     return u;
   }
 };
@@ -416,14 +422,16 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
     const uint32_t so_0 = (uint32_t)k * (uint32_t)plane_m;
     const uint32_t so_p = (uint32_t)phys(k + 1) * (uint32_t)plane_m;
     const bool wall_d = walls && k == 0, wall_u = walls && k == nz - 1;
-    // store pair (a, b) as direction q of node slot xs at plane offset so
-    auto store = [&](int q, uint32_t so, int xs, float a, float b) {
+    // store pair (a, b) as direction q of node slot xs at plane offset so;
+    // (xa, xb) is what the rest pair counts as the pair's old value (the
+    // decoded word of the direction, plus the wall's change to g at a wall)
+    auto store = [&](int q, uint32_t so, int xs, float a, float b, float xa, float xb) {
       const rsrc_t r = mkrsrc(row_start(out, row_m, q + (int)W::kRowOff));
       if constexpr (W::kDev) {
-        float ra, rb;
-        const S wv = W::enc_res(a, b, P.one, ra, rb);
-        rf += ra;
-        rg += rb;
+        float da, db;
+        const S wv = W::enc_diff(a, b, P.one, xa, xb, da, db);
+        rf += da;
+        rg += db;
         if (whole_lines(xs))
           BufIO<S>::template st<kNonTemporal>(r, xyb[xs], so, wv);
         else
@@ -451,9 +459,13 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
       const float dgb = fmaf(P.omega_g, xg[lb] - (gs - ga), -wS);
       const float fna = xf[l] - dfa, fnb = xf[lb] - dfb;
       const float gna = xg[l] - dga, gnb = xg[lb] - dgb;
-      // what the pairs give up (the 16-bit stores add their rounding)
-      rf += dfa + dfb;
-      rg += dga + dgb;
+      // what the pairs give up: FP32 sums the collision's changes (its stores
+      // are exact); the 16-bit forms sum old minus stored value per word in
+      // the store (collision change and rounding at once)
+      if constexpr (!W::kDev) {
+        rf += dfa + dfb;
+        rg += dga + dgb;
+      }
       // push: direction l from node x goes to x + c_l; at a wall it comes
       // back to x in the opposite direction (anti-bounce-back for g about
       // w_l rho_kappa T_wall)
@@ -461,18 +473,23 @@ __global__ __launch_bounds__(TX * TY) void k_pipe(const char* __restrict__ in,
       for (int h = 0; h < 2; ++h) {
         const int d = h ? lb : l;
         const float fn = h ? fnb : fna, gn = h ? gnb : gna;
+        const float xa = xf[d], xb = xg[d];
         if (CZ[d] == 0) {
-          store(d, so_0, xy_slot(d), fn, gn);
+          store(d, so_0, xy_slot(d), fn, gn, xa, xb);
         } else if (CZ[d] > 0) {
-          if (wall_u)
-            store(OPP[d], so_0, 0, fn, -gn + 2.f * w * P.rho_kappa * (P.T_u - P.T_ref0));
-          else
-            store(d, so_p, xy_slot(d), fn, gn);
+          if (wall_u) {
+            const float gb = -gn + 2.f * w * P.rho_kappa * (P.T_u - P.T_ref0);
+            store(OPP[d], so_0, 0, fn, gb, xa, xb + (gb - gn));
+          } else {
+            store(d, so_p, xy_slot(d), fn, gn, xa, xb);
+          }
         } else {
-          if (wall_d)
-            store(OPP[d], so_0, 0, fn, -gn + 2.f * w * P.rho_kappa * (P.T_d - P.T_ref0));
-          else
-            store(d, so_m, xy_slot(d), fn, gn);
+          if (wall_d) {
+            const float gb = -gn + 2.f * w * P.rho_kappa * (P.T_d - P.T_ref0);
+            store(OPP[d], so_0, 0, fn, gb, xa, xb + (gb - gn));
+          } else {
+            store(d, so_m, xy_slot(d), fn, gn, xa, xb);
+          }
         }
       }
     }
