@@ -175,6 +175,32 @@ def bandwidth_references(lbm, n, gib=8, reps=5):
             "rows19_state_gbs": rows19_state}
 
 
+def diagnostics_timing(lbm, n, reps=5):
+    """Wall time of one step followed by one FP64 diagnostic on a new state
+    (so rho, E and psi are recomputed once), for lbm_moments and lbm_nusselt,
+    FP32 and FP16 storage; one JSON line each."""
+    import torch
+    rho_mean = workload_params(lbm, n, "fp32").rho_ref
+    rho0 = lbm.lbm_seeded_density(n, n, n, 1234, rho_mean, 0.01).reshape(-1)
+    for st in ("fp32", "fp16dev"):
+        lat = lbm.Lattice(workload_params(lbm, n, st), rho0)
+        lat.step(2)
+        for what in ("moments", "nusselt"):
+            fn = (lambda: lat.moments()) if what == "moments" else (lambda: lat.nusselt())
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                lat.step(1)
+                fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            print(json.dumps({"storage": st, "diagnostic": what, "nodes": n ** 3,
+                              "ms_step_plus_diagnostic": round(ms, 3)}), flush=True)
+        del lat
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(seconds=15.0, n=64, max_steps=None):
     """FP64 oracle on the host, n^3 sample of the same physics, stepped for
     about `seconds` (or max_steps) after one warm-up step."""
@@ -217,6 +243,9 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time kernel/tile variants")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the library's plain 2 GiB copy (calibrates HBM byte counters)")
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="only time one step plus each FP64 diagnostic (lbm_moments, lbm_nusselt) "
+                         "at --size, FP32 and FP16 storage, one JSON line each")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 CPU oracle at 32^3, 64^3 (100 steps) and 128^3 "
                          "(20 steps), one JSON line each")
@@ -261,6 +290,9 @@ def main():
 
     lbm.load_library()
     n = args.size
+    if args.diagnostics:
+        diagnostics_timing(lbm, n)
+        return
     print(f"bench: generating {n}^3 seeded density field", file=sys.stderr, flush=True)
     rho_mean = workload_params(lbm, n, "fp32").rho_ref
     # the same field as seeded_density (bit for bit), generated on the device
