@@ -135,6 +135,31 @@ def test_tiles_and_chunks_bit_identical(glbm, storage):
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
+def test_default_launch_shape_bit_identical(glbm, storage):
+    """512 x 516 x 16 with the default 128 x 4 tiles: 516 tiles, three rounds of
+    the GPU's 256 resident work-groups if the column is not split, and not a
+    multiple of 8.  The default z chunking (which splits the 16 planes in
+    two: 1032 work-groups), one chunk (516 work-groups, so the XCD tile map
+    takes its uneven form) and 4-plane chunks give the same state bit for
+    bit after 3 steps."""
+    nx, ny, nz = 512, 516, 16
+    rho0 = synth.noisy_density(nx, ny, nz, 1.9, 0.05, 12)
+    kw = _kw(tau_nu=0.7, tau_kappa=0.9, gravity=1e-4)
+    ref = None
+    for zc in (0, 16, 4):
+        print(f"case: pipelined {storage} {nx}x{ny}x{nz} z_chunk={zc}", flush=True)
+        lat = _gpu(glbm, nx, ny, nz, rho0, 3, _storage(glbm, storage), z_chunk=zc, rho_ref=1.9,
+                   T_ref=0.9 * TC, **kw)
+        s = lat.state()
+        if ref is None:
+            ref = s.clone()
+        else:
+            assert torch.equal(s, ref), zc
+        del lat, s
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
 def test_variants_pipelined(glbm, storage):
     """Wetting walls with the original Shan-Chen pseudopotential, and the
     force-form coupling T_lat = 1/3: 20 x 12 x 16, 60 steps."""
