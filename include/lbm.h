@@ -124,10 +124,13 @@ typedef struct lbm_params {
   int32_t kernel;
   int32_t tile_x;      /* fused-kernel tile width: 0 (default 64), 32 or 64 */
   int32_t tile_y;      /* fused-kernel tile height: 0 (default), 1..32, see lbm_init */
-  int32_t z_chunk;     /* planes per fused-kernel work-group column; 0 = the whole
-                          height, split into chunks of at least 4 planes when
-                          the lattice has fewer tiles than the GPU holds work-groups
-                          of this kernel at once (the runtime's occupancy) */
+  int32_t z_chunk;     /* planes per fused-kernel work-group column; 0 = chosen at
+                          init: the chunking (chunks of at least 4 planes) that
+                          makes the launch shortest, counted as rounds of the
+                          work-groups the GPU holds at once (the runtime's
+                          occupancy) times the planes each marches plus its two
+                          halo planes; the whole height when the tiles fill
+                          whole rounds */
   int32_t adjoint;     /* 1 = reserve workspace for the lbm_adjoint_* entry points */
   double tau_nu, tau_kappa;
   double G;
